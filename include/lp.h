@@ -1,0 +1,215 @@
+/*
+ * lp.h -- C ABI of liblp.so, the MI355X (gfx950) hot path of the lunar
+ * nanosecond-pulse pipeline of Winchen et al., "Realtime processing of
+ * LOFAR data for the detection of nano-second pulses from the Moon"
+ * (arXiv:1612.06592).
+ *
+ * Per block of station subband data the path is
+ *   lp_beamform   -> tied-array beams (Sec. 3, first paragraph: each station
+ *                    signal summed with a complex weight set by the station
+ *                    position and the beam direction, 8 N_S FLOP per sample)
+ *   lp_dedisperse -> ionospheric de-dispersion (Sec. 3: multiplication in the
+ *                    frequency domain by an STEC-dependent complex weight,
+ *                    repeated over trial STEC values)
+ *   lp_synthesize -> time-domain synthesis from the polyphase-filtered
+ *                    subbands (Sec. 2 and Sec. 3, PPF inversion), fused with
+ *                    the Hilbert envelope and per-window peak finding
+ *   lp_trigger    -> trigger list for the transient-buffer read-out (Sec. 2)
+ * and lp_server_* / lp_stream_* run that chain for many concurrent
+ * observation streams with their state resident on the device.
+ *
+ * Conventions (the paper leaves them open):
+ *   - Subband k of the 1024-point critically sampled station PPF has RF
+ *     centre f0 + k * fs / M (f0 = 100 MHz, fs = 200 MHz: second Nyquist
+ *     zone with the spectral flip undone); a subband sample lasts M / fs.
+ *   - Beam weight of input (station s, polarisation p) toward direction n:
+ *     a_sp exp(-2 pi i frac(f_k (r_s . n) / c)), r_s in ENU metres,
+ *     n = (cos el sin az, cos el cos az, sin el).
+ *   - De-dispersion: overlap-save with N_fft = 4096, hop 2048 and a bulk
+ *     delay of D = 1024 subband samples; bin q (signed q_s, RF frequency
+ *     f_k + q_s fs / (M N_fft)) is multiplied by
+ *     exp(-2 pi i [kappa T / (f_k + nu_q) + q_s D / N_fft]), kappa =
+ *     e^2 / (8 pi^2 eps0 m_e) * 1e16 / c per TECU.
+ *   - Synthesis: Z_m[n] = sum_k d_k[m] e^{+2 pi i k n / M} and
+ *     z[mM + n] = sum_{t<16} g[tM + n] Z_{m-t}[n] with g = M h, h the
+ *     Kaiser(beta)-windowed sinc prototype of the station PPF (sum h = 1).
+ *     The real 5 ns series is 2 Re z and the analytic envelope |2 z|.
+ *   - Trigger: sigma^2 = mean of (2 Re z)^2 over the block's valid samples;
+ *     windows are the M-sample frames; a window fires when its envelope
+ *     maximum exceeds k_sigma * sigma; a run of fired windows gives one
+ *     trigger at its maximum; trials of one beam within M samples merge.
+ *     The reported sample is the ADC index at the array origin:
+ *     frame * M + n - M * 16 - D * M.  Frames whose stream index is below
+ *     D + 16 (start-up of a fresh stream) never fire and are not in sigma.
+ *
+ * Memory: every data, state and output buffer is device memory owned by
+ * the caller (e.g. torch tensors); the library never frees them.  Unless
+ * stated otherwise arguments named *_state are read and updated in place
+ * and are all-zero for a fresh stream.  Descriptors (lp_array, lp_band,
+ * lp_dir, TEC lists) are host memory read during the call only.  Device
+ * tables derived from descriptors (beam weights, chirp constants) are
+ * cached inside the lp_ctx.
+ *
+ * Errors: nothing throws across the ABI.  Argument errors return
+ * LP_EINVAL synchronously and leave every buffer untouched; the message is
+ * available from lp_last_error() (thread-local).  Kernel launches are
+ * asynchronous on the caller's hipStream_t (passed as void*, NULL = the
+ * null stream); device faults surface at the caller's next
+ * synchronisation.  Entry points taking a ctx are thread-safe for distinct
+ * streams.
+ */
+#ifndef LP_H
+#define LP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lp_status;
+#define LP_OK 0
+#define LP_EINVAL (-1)   /* bad argument                                  */
+#define LP_ENOMEM (-2)   /* device allocation failed                      */
+#define LP_EAGAIN (-3)   /* does not fit now (serving admission)          */
+#define LP_EHIP (-4)     /* HIP runtime error                             */
+#define LP_ECLOSED (-5)  /* stream or server closed                       */
+#define LP_ETIMEOUT (-6) /* nothing completed within the timeout          */
+
+/* Sample types of the station subband input. */
+#define LP_CI8 1  /* complex int8: (re, im) int8 pairs                     */
+#define LP_CI16 2 /* complex int16: (re, im) int16 pairs                   */
+
+/* Beamformer arithmetic. */
+#define LP_FP32 0      /* FP32 inputs and weights on the vector ALUs       */
+#define LP_FP16_MFMA 1 /* FP16 inputs and weights, FP32 accumulation on the
+                          matrix cores                                     */
+
+/* Fixed stream geometry of this library. */
+#define LP_M 1024      /* PPF channels (subband sample = LP_M ADC samples) */
+#define LP_TAPS 16     /* PPF taps per channel                              */
+#define LP_NFFT 4096   /* de-dispersion FFT length                          */
+#define LP_HOP 2048    /* de-dispersion hop; n_t must be a multiple of it   */
+#define LP_DELAY 1024  /* de-dispersion bulk delay in subband samples       */
+
+/* lp_dedisperse flags */
+#define LP_DD_KEEP_TAIL 1 /* read the tail state but do not update it      */
+
+typedef struct lp_ctx lp_ctx;
+
+typedef struct {
+  int32_t n_st;        /* stations                                         */
+  int32_t n_pol;       /* polarisations per station (both summed per beam) */
+  const double *enu_m; /* [n_st][3] station positions, ENU metres          */
+  const float *gain;   /* [n_st * n_pol] real input gains, or NULL (= 1)   */
+} lp_array;
+
+typedef struct {
+  int32_t n_sb;        /* number of selected subbands                      */
+  const int32_t *k;    /* [n_sb] subband ids, strictly ascending, 1..511   */
+  double f0_hz;        /* RF frequency of subband 0 (100e6)                */
+  double fs_hz;        /* ADC sample rate (200e6)                          */
+  int32_t M;           /* must be LP_M                                     */
+  int32_t taps;        /* must be LP_TAPS                                  */
+  double kaiser_beta;  /* prototype window parameter (9)                   */
+} lp_band;
+
+typedef struct {
+  double az_rad; /* azimuth from North through East                         */
+  double el_rad; /* elevation                                               */
+} lp_dir;
+
+typedef struct {
+  int64_t sample; /* ADC index at the array origin (stream time)          */
+  int32_t beam;
+  int32_t tec;    /* index into the TEC trial list                         */
+  float snr;      /* envelope / sigma at the trigger                       */
+  float peak;     /* envelope at the trigger                               */
+} lp_trig;
+
+/* Thread-local message of the last failing call on this thread. */
+const char *lp_last_error(void);
+const char *lp_version(void);
+
+/* Context on one HIP device: prototype taps, FFT twiddles and the cache of
+ * beam-weight and chirp tables.  Returns LP_EHIP if the device is absent. */
+lp_status lp_ctx_create(int32_t hip_device, lp_ctx **out);
+void lp_ctx_destroy(lp_ctx *ctx);
+
+/* ---- sizing helpers (bytes of caller-allocated device buffers) -------- */
+/* y of lp_beamform: cf32 [n_beams][n_sb][n_t]                              */
+size_t lp_beam_bytes(int32_t n_beams, int32_t n_sb, int64_t n_t);
+/* tail_state of lp_dedisperse: cf32 [n_beams][n_sb][LP_NFFT - LP_HOP]      */
+size_t lp_dd_state_bytes(int32_t n_beams, int32_t n_sb);
+/* d of lp_dedisperse: cf32 [n_beams][n_tec][n_sb][n_t]                     */
+size_t lp_dd_bytes(int32_t n_beams, int32_t n_tec, int32_t n_sb, int64_t n_t);
+/* hist_state of lp_synthesize: cf32 [n_series][n_sb][16]                   */
+size_t lp_syn_state_bytes(int32_t n_series, int32_t n_sb);
+/* cand of lp_synthesize / lp_trigger: per series and frame the envelope
+ * maximum (f32) and its offset in the frame (i32), then per series and
+ * 16-frame chunk the FP32 sum of (2 Re z)^2 over valid samples.          */
+size_t lp_cand_bytes(int32_t n_series, int64_t n_t);
+/* work of lp_trigger                                                       */
+size_t lp_trigger_work_bytes(int32_t n_beams, int32_t n_tec);
+
+/* ---- the hot path ------------------------------------------------------ */
+
+/* Multi-beam beamformer (paper Sec. 3, beamforming paragraph).
+ *   x : device, [n_sb][n_t][n_st][n_pol] complex int (dtype LP_CI8 or
+ *       LP_CI16), re/im interleaved, inputs contiguous.
+ *   y : device, cf32 [n_beams][n_sb][n_t] (lp_beam_bytes), overwritten.
+ *   prec: LP_FP32 or LP_FP16_MFMA.  In FP16 each input's weights are scaled
+ *       to unit peak magnitude by a power of two that is moved, exactly, onto
+ *       the input's samples (int8 and |int16| <= 2048 are exact in FP16).
+ * Requires n_st * n_pol <= 128, n_beams <= 64 per call, n_t % 128 == 0, and
+ * n_st * n_pol * sizeof(sample) a multiple of 4 bytes (else LP_EINVAL).   */
+lp_status lp_beamform(lp_ctx *ctx, const lp_array *array, const lp_band *band,
+                      const lp_dir *beams, int32_t n_beams, const void *x,
+                      int32_t dtype, int64_t n_t, int32_t prec, void *y,
+                      void *hip_stream);
+
+/* Per-subband overlap-save de-dispersion at n_tec trial STEC values (paper
+ * Sec. 3, dispersion paragraph).
+ *   y    : device cf32 [n_beams][n_sb][n_t] (the beamformer output).
+ *   tail : device cf32 state [n_beams][n_sb][2048]: the last 2048 samples of
+ *          the previous block; updated unless flags has LP_DD_KEEP_TAIL.
+ *   d    : device cf32 [n_beams][n_tec][n_sb][n_t] (lp_dd_bytes).  Output
+ *          sample t corresponds to input time t - LP_DELAY.
+ * n_t must be a positive multiple of LP_HOP; tec_tecu values in [0, 1000]. */
+lp_status lp_dedisperse(lp_ctx *ctx, const lp_band *band,
+                        const double *tec_tecu, int32_t n_tec, const void *y,
+                        int32_t n_beams, int64_t n_t, void *tail,
+                        int32_t flags, void *d, void *hip_stream);
+
+/* Synthesis filterbank, envelope and per-window peaks (paper Sec. 2-3, PPF
+ * inversion; this library uses the one-shot synthesis filterbank g = M h).
+ *   d      : device cf32 [n_series][n_sb][n_t] (series = beam * n_tec + tec).
+ *   frame0 : stream index of the block's first subband sample.
+ *   hist   : device cf32 state [n_series][n_sb][16], updated.
+ *   x_out  : device f32 [n_series][n_t * LP_M] real series 2 Re z, or NULL.
+ *   cand   : device, lp_cand_bytes(n_series, n_t), overwritten.           */
+lp_status lp_synthesize(lp_ctx *ctx, const lp_band *band, const void *d,
+                        int32_t n_series, int64_t n_t, int64_t frame0,
+                        void *hist, float *x_out, void *cand,
+                        void *hip_stream);
+
+/* Trigger rules over one block's candidates (paper Sec. 2: the trigger that
+ * reads out the transient buffers).
+ *   out      : device lp_trig[cap], ordered by (beam, sample).
+ *   n_out    : device int32, the true number of triggers (may exceed cap).
+ *   snr_out  : device f32 [n_beams][n_tec] peak envelope / sigma, or NULL.
+ *   best_tec : device i32 [n_beams] argmax of snr_out (lowest on ties), or
+ *              NULL.
+ *   sigma_out: device f32 [n_beams][n_tec], or NULL.
+ *   work     : device scratch of lp_trigger_work_bytes(n_beams, n_tec).   */
+lp_status lp_trigger(lp_ctx *ctx, const void *cand, int32_t n_beams,
+                     int32_t n_tec, int64_t n_t, int64_t frame0,
+                     float k_sigma, lp_trig *out, int32_t cap, int32_t *n_out,
+                     float *snr_out, int32_t *best_tec, float *sigma_out,
+                     void *work, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

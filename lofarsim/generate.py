@@ -28,6 +28,8 @@ Forward model (the instrument, not the hot path):
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -185,7 +187,6 @@ def generate(cfg: Workload, with_noise: bool = True,
     g_rng = np.random.default_rng(ch["geometry"])
     p_rng = np.random.default_rng(ch["pointing"])
     u_rng = np.random.default_rng(ch["pulses"])
-    n_rng = np.random.default_rng(ch["noise"])
     M, n_t = cfg.M, cfg.n_t
     enu = stations_in_disk(g_rng, cfg.n_st, cfg.disk_m)
     az0, el0 = moon_direction(p_rng)
@@ -225,9 +226,14 @@ def generate(cfg: Workload, with_noise: bool = True,
     itype = np.int8 if cfg.dtype == "ci8" else np.int16
     lim = 127 if cfg.dtype == "ci8" else 32767
     x = np.empty((cfg.n_sb, n_t, cfg.n_in, 2), dtype=itype)
-    for s in range(cfg.n_sb):
+    # One noise generator per subband (spawned from the noise seed), so the
+    # bytes do not depend on how many threads fill the block.
+    sb_seeds = ch["noise"].spawn(cfg.n_sb)
+
+    def fill(s):
         if with_noise:
-            v = n_rng.standard_normal((n_t, cfg.n_in, 2), dtype=np.float32)
+            rng = np.random.default_rng(sb_seeds[s])
+            v = rng.standard_normal((n_t, cfg.n_in, 2), dtype=np.float32)
             v *= np.float32(cfg.sigma)
         else:
             v = np.zeros((n_t, cfg.n_in, 2), dtype=np.float32)
@@ -242,6 +248,14 @@ def generate(cfg: Workload, with_noise: bool = True,
         np.rint(v, out=v)
         np.clip(v, -lim, lim, out=v)
         x[s] = v.astype(itype)
+
+    workers = max(1, min(16, os.cpu_count() or 1))
+    if cfg.n_sb * n_t * cfg.n_in < (1 << 22) or workers == 1:
+        for s in range(cfg.n_sb):
+            fill(s)
+    else:
+        with cf.ThreadPoolExecutor(workers) as ex:
+            list(ex.map(fill, range(cfg.n_sb)))
     return Block(cfg=cfg, x=x, enu=enu, az_el=az_el, k=k, tec=tec,
                  pulses=pulses, seeds=dict(entropy=int(entropy) if
                                           isinstance(entropy, int) else

@@ -1,0 +1,496 @@
+// Tied-array beamformer (Winchen et al. 2016, Sec. 3, beamforming
+// paragraph): per subband k and time t, y_b = sum_i w_{k,i,b} x_{k,t,i}
+// with the narrowband weight exp(-2 pi i frac(f_k (r_s . n_b) / c)).
+//
+// Per subband this is the complex GEMM [n_t x K] . [K x B], run as the real
+// GEMM [n_t x 2K] . [2K x 2B]: the input rows are already the interleaved
+// (re, im) int samples, and the weight matrix has blocks
+// [[w_re, w_im], [-w_im, w_re]].  LP_FP16_MFMA converts the ints to FP16
+// (exact for int8) and accumulates in FP32 with v_mfma_f32_16x16x16f16;
+// LP_FP32 does the same sums on the vector ALUs.
+#include <cmath>
+#include <cstring>
+
+#include "lp_internal.h"
+
+namespace lp {
+
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBfT = 128;        // time rows per tile
+constexpr int kBfThreads = 256;  // 4 waves
+constexpr int kBfKsMax = 16;     // up to 2K = 256 real rows (K <= 128)
+constexpr size_t kLdsMax = 160 * 1024;
+
+// ------------------------------------------------------------- weights
+
+__device__ inline void weight_value(const double *__restrict__ enu,
+                                    const double *__restrict__ azel,
+                                    const float *__restrict__ gain,
+                                    const double *__restrict__ wscale,
+                                    const int *__restrict__ kk, double f0,
+                                    double df, int n_pol, int s, int inp,
+                                    int b, float &wr, float &wi) {
+  int st = inp / n_pol;
+  double az = azel[2 * b], el = azel[2 * b + 1];
+  double nx = cos(el) * sin(az), ny = cos(el) * cos(az), nz = sin(el);
+  double proj = enu[3 * st] * nx + enu[3 * st + 1] * ny + enu[3 * st + 2] * nz;
+  double cyc = (f0 + (double)kk[s] * df) * proj / kC;
+  float r = (float)(cyc - rint(cyc));  // FP64 range reduction, then FP32
+  float sn, cs;
+  sincospif(2.0f * r, &sn, &cs);
+  float a = (gain ? gain[inp] : 1.0f) * (float)wscale[inp];
+  wr = a * cs;
+  wi = -a * sn;
+}
+
+// MFMA B-operand fragments: element ((s*NT + nt)*KS + ks)*256 + lane*4 + i
+// holds Wr[ks*16 + 4*(lane/16) + i][nt*16 + lane%16].
+__global__ void bf_weights_mfma_kernel(
+    const double *__restrict__ enu, const double *__restrict__ azel,
+    const float *__restrict__ gain, const double *__restrict__ wscale,
+    const int *__restrict__ kk, double f0, double df, int n_pol, int n_in,
+    int n_beams, int n_sb, int KS, int NT, _Float16 *__restrict__ wf) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long per_s = (long)NT * KS * 256;
+  if (idx >= per_s * n_sb) return;
+  int s = (int)(idx / per_s);
+  long rem = idx % per_s;
+  int nt = (int)(rem / (KS * 256));
+  rem %= KS * 256;
+  int ks = (int)(rem / 256);
+  int lane = (int)(rem % 256) / 4, i = (int)(rem % 4);
+  int krow = ks * 16 + 4 * (lane / 16) + i;
+  int ncol = nt * 16 + (lane % 16);
+  int inp = krow >> 1, xp = krow & 1, b = ncol >> 1, op = ncol & 1;
+  float v = 0.0f;
+  if (inp < n_in && b < n_beams) {
+    float wr, wi;
+    weight_value(enu, azel, gain, wscale, kk, f0, df, n_pol, s, inp, b, wr,
+                 wi);
+    v = (xp == 0) ? (op == 0 ? wr : wi) : (op == 0 ? -wi : wr);
+  }
+  wf[idx] = (_Float16)v;
+}
+
+// FP32 weights [s][in][b] (re, im).
+__global__ void bf_weights_fp32_kernel(
+    const double *__restrict__ enu, const double *__restrict__ azel,
+    const float *__restrict__ gain, const double *__restrict__ wscale,
+    const int *__restrict__ kk, double f0, double df, int n_pol, int n_in,
+    int n_beams, int n_sb, float2 *__restrict__ w) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)n_sb * n_in * n_beams) return;
+  int b = (int)(idx % n_beams);
+  int inp = (int)((idx / n_beams) % n_in);
+  int s = (int)(idx / ((long)n_beams * n_in));
+  float wr, wi;
+  weight_value(enu, azel, gain, wscale, kk, f0, df, n_pol, s, inp, b, wr, wi);
+  w[idx] = make_float2(wr, wi);
+}
+
+// --------------------------------------------------------- MFMA kernel
+
+// Vector load of VB bytes into a small register array.
+template <int VB, typename T>
+__device__ __forceinline__ void load_vec(T *dst, const char *src) {
+  if constexpr (VB == 16) {
+    int4 q = *reinterpret_cast<const int4 *>(src);
+    __builtin_memcpy(dst, &q, 16);
+  } else if constexpr (VB == 8) {
+    int2 q = *reinterpret_cast<const int2 *>(src);
+    __builtin_memcpy(dst, &q, 8);
+  } else {
+    int q = *reinterpret_cast<const int *>(src);
+    __builtin_memcpy(dst, &q, 4);
+  }
+}
+
+template <typename IT, int VB>
+__device__ inline void stage_tile_f16(const IT *__restrict__ src, int RK,
+                                      int RKP, int KS,
+                                      const _Float16 *__restrict__ xscale,
+                                      bool scaled, _Float16 *__restrict__ sm) {
+  constexpr int EPV = VB / (int)sizeof(IT);  // elements per vector
+  const int nvec = kBfT * RK / EPV;
+  const char *base = reinterpret_cast<const char *>(src);
+  for (int v = threadIdx.x; v < nvec; v += kBfThreads) {
+    int e0 = v * EPV;
+    int row = e0 / RK, col = e0 - row * RK;
+    IT raw[EPV];
+    load_vec<VB>(raw, base + (size_t)v * VB);
+    _Float16 hv[EPV];
+#pragma unroll
+    for (int i = 0; i < EPV; ++i) {
+      _Float16 h = (_Float16)(float)raw[i];
+      hv[i] = scaled ? h * xscale[col + i] : h;
+    }
+    _Float16 *dst = sm + row * RKP + col;
+    if constexpr (EPV % 8 == 0) {
+#pragma unroll
+      for (int i = 0; i < EPV; i += 8) {
+        int4 q;
+        __builtin_memcpy(&q, hv + i, 16);
+        *reinterpret_cast<int4 *>(dst + i) = q;
+      }
+    } else if constexpr (EPV == 4) {
+      int2 q;
+      __builtin_memcpy(&q, hv, 8);
+      *reinterpret_cast<int2 *>(dst) = q;
+    } else {
+      int q;
+      __builtin_memcpy(&q, hv, 4);
+      *reinterpret_cast<int *>(dst) = q;
+    }
+  }
+  // Zero the columns RK .. KS*16-1 (their weights are zero too, but stale
+  // LDS could hold NaN bit patterns).
+  int padc = KS * 16 - RK;
+  if (padc > 0)
+    for (int i = threadIdx.x; i < kBfT * padc; i += kBfThreads)
+      sm[(i / padc) * RKP + RK + (i % padc)] = (_Float16)0.0f;
+}
+
+// Grid: x = time-tile groups, y = subband.  Waves are laid out WM x WN over
+// (16-row m-tiles, 16-column n-tiles); each wave keeps its NPW n-tiles of
+// weight fragments in registers for all of its tiles.
+template <typename IT, int VB, int NPW>
+__global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
+    const IT *__restrict__ x, const half4 *__restrict__ wf,
+    const _Float16 *__restrict__ xscale, int scaled, float2 *__restrict__ y,
+    int n_sb, long n_t, int RK, int KS, int NT, int WN, int n_beams,
+    int tiles_per_wg) {
+  extern __shared__ _Float16 sm[];
+  const int RKP = KS * 16 + 8;
+  const int s = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wn = wave % WN, wm = wave / WN, WM = 4 / WN;
+  const int kq = lane >> 4, col16 = lane & 15;
+
+  half4 wreg[NPW][kBfKsMax];
+#pragma unroll
+  for (int p = 0; p < NPW; ++p) {
+    int nt = wn + p * WN;
+#pragma unroll
+    for (int ks = 0; ks < kBfKsMax; ++ks) {
+      half4 z = {0, 0, 0, 0};
+      wreg[p][ks] = (nt < NT && ks < KS)
+                        ? wf[((long)(s * NT + nt) * KS + ks) * 64 + lane]
+                        : z;
+    }
+  }
+
+  const int mt_per_wave = (kBfT / 16) / WM;
+  for (int tile = 0; tile < tiles_per_wg; ++tile) {
+    long t0 = ((long)blockIdx.x * tiles_per_wg + tile) * kBfT;
+    if (t0 >= n_t) break;
+    __syncthreads();
+    stage_tile_f16<IT, VB>(x + ((long)s * n_t + t0) * RK, RK, RKP, KS, xscale,
+                           scaled != 0, sm);
+    __syncthreads();
+    for (int mi = 0; mi < mt_per_wave; ++mi) {
+      int mt = wm * mt_per_wave + mi;
+      int row = mt * 16 + col16;
+      floatx4 acc[NPW];
+#pragma unroll
+      for (int p = 0; p < NPW; ++p) acc[p] = floatx4{0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < kBfKsMax; ++ks) {
+        if (ks < KS) {
+          half4 a = *reinterpret_cast<const half4 *>(sm + row * RKP + ks * 16 +
+                                                     4 * kq);
+#pragma unroll
+          for (int p = 0; p < NPW; ++p)
+            acc[p] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, wreg[p][ks],
+                                                           acc[p], 0, 0, 0);
+        }
+      }
+      // Lane holds D[4 kq + r][col16], r = 0..3.  Even columns are the real
+      // parts and odd columns the imaginary parts of beam col/2: swap half of
+      // the rows with the neighbour lane so each lane writes two complex.
+#pragma unroll
+      for (int p = 0; p < NPW; ++p) {
+        int nt = wn + p * WN;
+        int col = nt * 16 + col16;
+        bool odd = col & 1;
+        float s0 = odd ? acc[p][0] : acc[p][2];
+        float s1 = odd ? acc[p][1] : acc[p][3];
+        float r0 = __shfl_xor(s0, 1);
+        float r1 = __shfl_xor(s1, 1);
+        int b = col >> 1;
+        if (nt < NT && b < n_beams) {
+          long t = t0 + mt * 16 + 4 * kq + (odd ? 2 : 0);
+          float4 o = odd ? make_float4(r0, acc[p][2], r1, acc[p][3])
+                         : make_float4(acc[p][0], r0, acc[p][1], r1);
+          *reinterpret_cast<float4 *>(y + ((long)b * n_sb + s) * n_t + t) = o;
+        }
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------- FP32 kernel
+
+// Grid: x = time tiles of T = 256 / G rows, y = subband.  Thread (t, g)
+// forms beams g, g + G, ... for time t from the LDS-staged tile.
+template <typename IT, int VB>
+__global__ __launch_bounds__(kBfThreads) void bf_fp32_kernel(
+    const IT *__restrict__ x, const float2 *__restrict__ w,
+    float2 *__restrict__ y, int n_sb, long n_t, int n_in, int n_beams,
+    int G) {
+  extern __shared__ float smf[];
+  const int T = kBfThreads / G;
+  const int RK = 2 * n_in, RKP = RK + 1;
+  float *xs = smf;
+  float2 *ws = reinterpret_cast<float2 *>(smf + ((T * RKP + 1) & ~1));
+  const int s = blockIdx.y;
+  const long t0 = (long)blockIdx.x * T;
+  const int rows = (int)min((long)T, n_t - t0);
+  constexpr int EPV = VB / (int)sizeof(IT);
+  const char *base =
+      reinterpret_cast<const char *>(x + ((long)s * n_t + t0) * RK);
+  const int nvec = rows * RK / EPV;
+  for (int v = threadIdx.x; v < nvec; v += kBfThreads) {
+    int e0 = v * EPV, row = e0 / RK, col = e0 - row * RK;
+    IT raw[EPV];
+    load_vec<VB>(raw, base + (size_t)v * VB);
+#pragma unroll
+    for (int i = 0; i < EPV; ++i) xs[row * RKP + col + i] = (float)raw[i];
+  }
+  const float2 *wsrc = w + (long)s * n_in * n_beams;
+  for (int i = threadIdx.x; i < n_in * n_beams; i += kBfThreads) ws[i] = wsrc[i];
+  __syncthreads();
+  const int t = threadIdx.x % T, g = threadIdx.x / T;
+  if (t >= rows) return;
+  const float *xr = xs + t * RKP;
+  for (int b = g; b < n_beams; b += G) {
+    float ar = 0.f, ai = 0.f;
+    for (int i = 0; i < n_in; ++i) {
+      float2 wv = ws[i * n_beams + b];
+      float re = xr[2 * i], im = xr[2 * i + 1];
+      ar = fmaf(re, wv.x, ar);
+      ar = fmaf(-im, wv.y, ar);
+      ai = fmaf(re, wv.y, ai);
+      ai = fmaf(im, wv.x, ai);
+    }
+    y[((long)b * n_sb + s) * n_t + t0 + t] = make_float2(ar, ai);
+  }
+}
+
+// ---------------------------------------------------------------- plan
+
+template <typename T>
+static void put(std::vector<uint8_t> &v, const T &x) {
+  const uint8_t *p = reinterpret_cast<const uint8_t *>(&x);
+  v.insert(v.end(), p, p + sizeof(T));
+}
+
+lp_status get_bf_plan(lp_ctx *ctx, const lp_array *a, const lp_band *band,
+                      const lp_dir *beams, int n_beams, int prec,
+                      BfPlan **out) {
+  const int n_in = a->n_st * a->n_pol;
+  std::vector<uint8_t> key;
+  put(key, prec);
+  put(key, a->n_st);
+  put(key, a->n_pol);
+  for (int i = 0; i < 3 * a->n_st; ++i) put(key, a->enu_m[i]);
+  put(key, (int)(a->gain != nullptr));
+  if (a->gain)
+    for (int i = 0; i < n_in; ++i) put(key, a->gain[i]);
+  put(key, band->n_sb);
+  for (int i = 0; i < band->n_sb; ++i) put(key, band->k[i]);
+  put(key, band->f0_hz);
+  put(key, band->fs_hz);
+  put(key, n_beams);
+  for (int b = 0; b < n_beams; ++b) {
+    put(key, beams[b].az_rad);
+    put(key, beams[b].el_rad);
+  }
+  std::lock_guard<std::mutex> g(ctx->mu);
+  for (auto &p : ctx->bf)
+    if (p->key == key) {
+      *out = p.get();
+      return LP_OK;
+    }
+  auto p = std::make_unique<BfPlan>();
+  p->key = key;
+  p->prec = prec;
+  p->n_in = n_in;
+  p->n_beams = n_beams;
+  p->n_sb = band->n_sb;
+  p->KS = (2 * n_in + 15) / 16;
+  p->NT = (2 * n_beams + 15) / 16;
+
+  // Per-input power-of-two scale: weights divided by 2^e (|w| <= 1 in
+  // FP16), samples multiplied by 2^e at conversion (exact).
+  std::vector<double> wscale(n_in, 1.0);
+  std::vector<_Float16> xscale((size_t)p->KS * 16, (_Float16)1.0f);
+  if (a->gain && prec == LP_FP16_MFMA) {
+    for (int i = 0; i < n_in; ++i) {
+      double mag = std::fabs((double)a->gain[i]);
+      int e = 0;
+      if (mag > 0) e = (int)std::ceil(std::log2(mag));
+      if (e < -14 || e > 8)
+        return set_error(LP_EINVAL, "gain %g out of the FP16 scaling range",
+                         mag);
+      if (e != 0) p->scaled = true;
+      wscale[i] = std::ldexp(1.0, -e);
+      xscale[2 * i] = xscale[2 * i + 1] = (_Float16)std::ldexp(1.0, e);
+    }
+  }
+  DevBuf denu, dazel, dgain, dws, dk;
+  std::vector<double> azel(2 * n_beams);
+  for (int b = 0; b < n_beams; ++b) {
+    azel[2 * b] = beams[b].az_rad;
+    azel[2 * b + 1] = beams[b].el_rad;
+  }
+  LP_HIP(hipMalloc(&denu.p, 3 * a->n_st * 8));
+  LP_HIP(hipMalloc(&dazel.p, 2 * n_beams * 8));
+  LP_HIP(hipMalloc(&dws.p, n_in * 8));
+  LP_HIP(hipMalloc(&dk.p, band->n_sb * 4));
+  LP_HIP(hipMemcpy(denu.p, a->enu_m, 3 * a->n_st * 8, hipMemcpyHostToDevice));
+  LP_HIP(hipMemcpy(dazel.p, azel.data(), 2 * n_beams * 8, hipMemcpyHostToDevice));
+  LP_HIP(hipMemcpy(dws.p, wscale.data(), n_in * 8, hipMemcpyHostToDevice));
+  LP_HIP(hipMemcpy(dk.p, band->k, band->n_sb * 4, hipMemcpyHostToDevice));
+  if (a->gain) {
+    LP_HIP(hipMalloc(&dgain.p, n_in * 4));
+    LP_HIP(hipMemcpy(dgain.p, a->gain, n_in * 4, hipMemcpyHostToDevice));
+  }
+  double df = band->fs_hz / kM;
+  if (prec == LP_FP16_MFMA) {
+    long n = (long)band->n_sb * p->NT * p->KS * 256;
+    LP_HIP(hipMalloc(&p->w.p, n * 2));
+    LP_HIP(hipMalloc(&p->xscale.p, xscale.size() * 2));
+    LP_HIP(hipMemcpy(p->xscale.p, xscale.data(), xscale.size() * 2,
+                     hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(bf_weights_mfma_kernel, dim3((n + 255) / 256),
+                       dim3(256), 0, 0, denu.as<double>(), dazel.as<double>(),
+                       dgain.as<float>(), dws.as<double>(), dk.as<int>(),
+                       band->f0_hz, df, a->n_pol, n_in, n_beams, band->n_sb,
+                       p->KS, p->NT, p->w.as<_Float16>());
+  } else {
+    long n = (long)band->n_sb * n_in * n_beams;
+    LP_HIP(hipMalloc(&p->w.p, n * 8));
+    hipLaunchKernelGGL(bf_weights_fp32_kernel, dim3((n + 255) / 256),
+                       dim3(256), 0, 0, denu.as<double>(), dazel.as<double>(),
+                       dgain.as<float>(), dws.as<double>(), dk.as<int>(),
+                       band->f0_hz, df, a->n_pol, n_in, n_beams, band->n_sb,
+                       p->w.as<float2>());
+  }
+  LP_HIP(hipGetLastError());
+  LP_HIP(hipDeviceSynchronize());
+  *out = p.get();
+  ctx->bf.push_back(std::move(p));
+  return LP_OK;
+}
+
+template <typename IT>
+static lp_status launch_bf(const BfPlan *p, const void *x, long n_t, int n_sb,
+                           void *y, hipStream_t st) {
+  const int n_in = p->n_in, RK = 2 * n_in;
+  const int row_bytes = RK * (int)sizeof(IT);
+  const int vb = (row_bytes % 16 == 0) ? 16 : (row_bytes % 8 == 0) ? 8 : 4;
+  if (p->prec == LP_FP16_MFMA) {
+    const int NT = p->NT, KS = p->KS;
+    const int WN = (NT == 1) ? 1 : (NT == 2) ? 2 : 4;
+    const int npw = (NT + WN - 1) / WN;
+    const int tiles = (int)(n_t / kBfT);
+    const int tpw = tiles >= 4 ? 4 : 1;
+    dim3 grid((tiles + tpw - 1) / tpw, n_sb);
+    size_t shm = (size_t)kBfT * (KS * 16 + 8) * 2;
+    auto args = [&](auto kern) {
+      LP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)shm));
+      hipLaunchKernelGGL(kern, grid, dim3(kBfThreads), shm, st,
+                         static_cast<const IT *>(x), p->w.as<const half4>(),
+                         p->xscale.as<const _Float16>(), (int)p->scaled,
+                         static_cast<float2 *>(y), n_sb, n_t, RK, KS, NT, WN,
+                         p->n_beams, tpw);
+      return LP_OK;
+    };
+    lp_status rc;
+    if (npw == 1)
+      rc = (vb == 16)  ? args(bf_mfma_kernel<IT, 16, 1>)
+           : (vb == 8) ? args(bf_mfma_kernel<IT, 8, 1>)
+                       : args(bf_mfma_kernel<IT, 4, 1>);
+    else
+      rc = (vb == 16)  ? args(bf_mfma_kernel<IT, 16, 2>)
+           : (vb == 8) ? args(bf_mfma_kernel<IT, 8, 2>)
+                       : args(bf_mfma_kernel<IT, 4, 2>);
+    if (rc) return rc;
+  } else {
+    int G = p->n_beams >= 4 ? 4 : p->n_beams >= 2 ? 2 : 1;
+    int T = kBfThreads / G;
+    auto lds = [&](int T_) {
+      return (((size_t)T_ * (RK + 1) + 1) & ~(size_t)1) * 4 +
+             (size_t)n_in * p->n_beams * 8;
+    };
+    while (lds(T) > kLdsMax && T > 16) {
+      T /= 2;
+      G *= 2;
+    }
+    size_t shm = lds(T);
+    if (shm > kLdsMax)
+      return set_error(LP_EINVAL, "FP32 beamformer tile too large for LDS");
+    dim3 grid((unsigned)((n_t + T - 1) / T), n_sb);
+    auto args = [&](auto kern) {
+      LP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)shm));
+      hipLaunchKernelGGL(kern, grid, dim3(kBfThreads), shm, st,
+                         static_cast<const IT *>(x), p->w.as<const float2>(),
+                         static_cast<float2 *>(y), n_sb, n_t, n_in,
+                         p->n_beams, G);
+      return LP_OK;
+    };
+    lp_status rc = (vb == 16)  ? args(bf_fp32_kernel<IT, 16>)
+                   : (vb == 8) ? args(bf_fp32_kernel<IT, 8>)
+                               : args(bf_fp32_kernel<IT, 4>);
+    if (rc) return rc;
+  }
+  LP_HIP(hipGetLastError());
+  return LP_OK;
+}
+
+}  // namespace lp
+
+using namespace lp;
+
+extern "C" lp_status lp_beamform(lp_ctx *ctx, const lp_array *array,
+                                 const lp_band *band, const lp_dir *beams,
+                                 int32_t n_beams, const void *x,
+                                 int32_t dtype, int64_t n_t, int32_t prec,
+                                 void *y, void *hip_stream) {
+  if (!ctx || !array || !beams || !x || !y)
+    return set_error(LP_EINVAL, "lp_beamform: NULL argument");
+  lp_status rc = check_band(band);
+  if (rc) return rc;
+  if (array->n_st <= 0 || array->n_pol <= 0 || !array->enu_m)
+    return set_error(LP_EINVAL, "lp_beamform: bad array descriptor");
+  const int n_in = array->n_st * array->n_pol;
+  if (n_in > 128)
+    return set_error(LP_EINVAL, "lp_beamform: n_st*n_pol = %d > 128", n_in);
+  if (n_beams <= 0 || n_beams > 64)
+    return set_error(LP_EINVAL, "lp_beamform: n_beams %d not in 1..64",
+                     n_beams);
+  if (dtype != LP_CI8 && dtype != LP_CI16)
+    return set_error(LP_EINVAL, "lp_beamform: dtype %d", dtype);
+  if (prec != LP_FP32 && prec != LP_FP16_MFMA)
+    return set_error(LP_EINVAL, "lp_beamform: precision %d", prec);
+  if (n_t <= 0 || n_t % kBfT != 0)
+    return set_error(LP_EINVAL, "lp_beamform: n_t %lld not a multiple of %d",
+                     (long long)n_t, kBfT);
+  if ((2 * n_in * (dtype == LP_CI8 ? 1 : 2)) % 4 != 0)
+    return set_error(LP_EINVAL,
+                     "lp_beamform: a time row must be a multiple of 4 bytes");
+  if (reinterpret_cast<uintptr_t>(x) % 16 || reinterpret_cast<uintptr_t>(y) % 16)
+    return set_error(LP_EINVAL, "lp_beamform: x and y must be 16-byte aligned");
+  if ((rc = set_device(ctx))) return rc;
+  BfPlan *p = nullptr;
+  if ((rc = get_bf_plan(ctx, array, band, beams, n_beams, prec, &p))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (dtype == LP_CI8) return launch_bf<int8_t>(p, x, n_t, band->n_sb, y, st);
+  return launch_bf<int16_t>(p, x, n_t, band->n_sb, y, st);
+}

@@ -1,0 +1,160 @@
+// Ionospheric de-dispersion (Winchen et al. 2016, Sec. 3, dispersion
+// paragraph): per beam and subband the series is multiplied in the
+// frequency domain by the complex weight of the trial STEC.  Overlap-save:
+// each hop of 2048 new samples forms a 4096-point buffer with the previous
+// 2048 samples, is transformed once, and for every trial is multiplied by
+//   exp(-2 pi i [kappa T / (f_k + nu_q) + q_s D / 4096])
+// and transformed back; the last 2048 outputs are kept.
+//
+// One 256-thread workgroup per (beam, subband, hop).  Each thread owns 16
+// points; the 4096-point transform is three radix-16 Stockham passes with
+// two exchanges through a padded 34 KB LDS tile.  The forward spectrum
+// stays in registers across all trials.
+#include <cmath>
+
+#include "fft_dev.h"
+#include "lp_internal.h"
+
+namespace lp {
+
+constexpr int kDdThreads = 256;
+constexpr int kDdLds = 4096 + 256;  // pad16 of 4095 is 4350
+
+// 4096-point transform of v[r] = in[j + 256 r] (j = thread); on return
+// v[r] = out[j + 256 r].  Unnormalised; INV selects exp(+2 pi i ...).
+template <bool INV>
+__device__ __forceinline__ void fft4096(float2 *v, float2 *lds,
+                                        const float2 *__restrict__ tw, int j) {
+  // Pass 0 (Ns = 1): no twiddle; write to (16 j + r).
+  dft16<INV>(v);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) lds[pad16(16 * j + r)] = v[r];
+  __syncthreads();
+  // Pass 1 (Ns = 16).
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = lds[pad16(j + 256 * r)];
+  twiddle16<INV>(v, tw, (j & 15) * 16);
+  dft16<INV>(v);
+  __syncthreads();
+  {
+    int base = (j >> 4) * 256 + (j & 15);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) lds[pad16(base + 16 * r)] = v[r];
+  }
+  __syncthreads();
+  // Pass 2 (Ns = 256): output index j + 256 r stays in registers.
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = lds[pad16(j + 256 * r)];
+  twiddle16<INV>(v, tw, j);
+  dft16<INV>(v);
+}
+
+__global__ __launch_bounds__(kDdThreads)
+__attribute__((amdgpu_waves_per_eu(4, 8))) void dd_kernel(
+    const float2 *__restrict__ y, float2 *__restrict__ tail, int update_tail,
+    float2 *__restrict__ d, const float2 *__restrict__ tw,
+    const float *__restrict__ base, const float *__restrict__ afac,
+    const float *__restrict__ rfk, int n_sb, int n_tec, long n_t, int n_hop,
+    long n_blocks) {
+  __shared__ float2 lds[kDdLds];
+  const long bid = xcd_remap(blockIdx.x, n_blocks);
+  const int h = (int)(bid % n_hop);
+  const long bs = bid / n_hop;          // beam * n_sb + subband
+  const int s = (int)(bs % n_sb);
+  const int b = (int)(bs / n_sb);
+  const int j = threadIdx.x;
+  const float2 *ys = y + bs * n_t;
+  float2 *tl = tail + bs * kHist;
+  const long hs = (long)h * kHop;
+
+  float2 v[16];
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+    v[r] = (h == 0) ? tl[j + 256 * r] : ys[hs - kHist + j + 256 * r];
+#pragma unroll
+  for (int r = 8; r < 16; ++r) v[r] = ys[hs + j + 256 * (r - 8)];
+
+  fft4096<false>(v, lds, tw, j);
+
+  // Hop 0 read the old tail above (and every thread has passed the
+  // barriers inside the transform), so it can now store the new one.
+  if (update_tail && h == 0) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) tl[j + 256 * r] = ys[n_t - kHist + j + 256 * r];
+  }
+
+  float2 U[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) U[r] = v[r];
+  const float rf = rfk[s];
+  const float scale = 1.0f / 4096.0f;
+  for (int jt = 0; jt < n_tec; ++jt) {
+    const int jo = opaque(j);
+    const float bse = base[jt * n_sb + s], A = afac[jt * n_sb + s];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      int q = jo + 256 * r;
+      int qs = (q < 2048) ? q : q - 4096;
+      float x = (float)qs * rf;                     // nu_q / f_k
+      // frac(kappa T/(f_k+nu)) = frac(A) - A x / (1 + x); the bulk delay
+      // q_s D / 4096 = q_s / 4 contributes (q_s mod 4) / 4 exactly.
+      float c = bse - A * x / (1.0f + x) + 0.25f * (float)(qs & 3);
+      c -= rintf(c);
+      float sn, cs;
+      __sincosf(6.283185307179586f * c, &sn, &cs);
+      v[r] = cmul(U[r], make_float2(cs, -sn));
+    }
+    __syncthreads();  // previous trial's last LDS reads are done
+    fft4096<true>(v, lds, tw, jo);
+    float2 *out = d + (((long)b * n_tec + jt) * n_sb + s) * n_t + hs;
+#pragma unroll
+    for (int r = 8; r < 16; ++r)
+      out[j + 256 * (r - 8)] = make_float2(v[r].x * scale, v[r].y * scale);
+  }
+}
+
+}  // namespace lp
+
+using namespace lp;
+
+extern "C" lp_status lp_dedisperse(lp_ctx *ctx, const lp_band *band,
+                                   const double *tec_tecu, int32_t n_tec,
+                                   const void *y, int32_t n_beams,
+                                   int64_t n_t, void *tail, int32_t flags,
+                                   void *d, void *hip_stream) {
+  if (!ctx || !tec_tecu || !y || !tail || !d)
+    return set_error(LP_EINVAL, "lp_dedisperse: NULL argument");
+  lp_status rc = check_band(band);
+  if (rc) return rc;
+  if (n_tec <= 0 || n_tec > 4096)
+    return set_error(LP_EINVAL, "lp_dedisperse: n_tec %d", n_tec);
+  for (int j = 0; j < n_tec; ++j)
+    if (!(tec_tecu[j] >= 0.0 && tec_tecu[j] <= 1000.0))
+      return set_error(LP_EINVAL, "lp_dedisperse: TEC %g outside [0, 1000]",
+                       tec_tecu[j]);
+  if (n_beams <= 0)
+    return set_error(LP_EINVAL, "lp_dedisperse: n_beams %d", n_beams);
+  if (n_t <= 0 || n_t % kHop != 0)
+    return set_error(LP_EINVAL,
+                     "lp_dedisperse: n_t %lld not a positive multiple of %d",
+                     (long long)n_t, kHop);
+  if (flags & ~LP_DD_KEEP_TAIL)
+    return set_error(LP_EINVAL, "lp_dedisperse: unknown flags 0x%x", flags);
+  if ((rc = set_device(ctx))) return rc;
+  DdPlan *p = nullptr;
+  if ((rc = get_dd_plan(ctx, band, tec_tecu, n_tec, &p))) return rc;
+  const int n_hop = (int)(n_t / kHop);
+  const long nb = (long)n_beams * band->n_sb * n_hop;
+  if (nb > 0x7fffffffL)
+    return set_error(LP_EINVAL, "lp_dedisperse: grid too large");
+  hipLaunchKernelGGL(dd_kernel, dim3((unsigned)nb), dim3(kDdThreads), 0,
+                     static_cast<hipStream_t>(hip_stream),
+                     static_cast<const float2 *>(y), static_cast<float2 *>(tail),
+                     (flags & LP_DD_KEEP_TAIL) ? 0 : 1, static_cast<float2 *>(d),
+                     ctx->tw4096.as<const float2>(), p->base.as<const float>(),
+                     p->afac.as<const float>(), p->rfk.as<const float>(),
+                     band->n_sb, n_tec, (long)n_t, n_hop, nb);
+  LP_HIP(hipGetLastError());
+  return LP_OK;
+}

@@ -1,0 +1,132 @@
+// Register-level DFT butterflies and Stockham passes shared by the
+// de-dispersion (4096-point) and synthesis (1024-point) kernels.
+//
+// A Stockham pass of radix R over an N-point transform, with Ns the size
+// of the sub-transforms already formed, lets butterfly j (0 <= j < N/R)
+// read in[j + r N/R], twiddle element r by exp(s 2 pi i (j mod Ns) r /
+// (Ns R)), do an R-point DFT and write out[(j / Ns) Ns R + (j mod Ns) +
+// r Ns]; Ns = 1, R1, R1 R2, ... yields the natural-order DFT.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace lp {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) {
+  return make_float2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ float2 csub(float2 a, float2 b) {
+  return make_float2(a.x - b.x, a.y - b.y);
+}
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
+// 4-point DFT in place; INV selects the +i kernel.
+template <bool INV>
+__device__ __forceinline__ void dft4(float2 &a, float2 &b, float2 &c,
+                                     float2 &d) {
+  float2 t0 = cadd(a, c), t1 = csub(a, c), t2 = cadd(b, d), t3 = csub(b, d);
+  a = cadd(t0, t2);
+  c = csub(t0, t2);
+  if (!INV) {  // X1 = t1 - i t3, X3 = t1 + i t3
+    b = make_float2(t1.x + t3.y, t1.y - t3.x);
+    d = make_float2(t1.x - t3.y, t1.y + t3.x);
+  } else {
+    b = make_float2(t1.x - t3.y, t1.y + t3.x);
+    d = make_float2(t1.x + t3.y, t1.y - t3.x);
+  }
+}
+
+// exp(-2 pi i m / 16) for m = 0..15 (cos, -sin).
+__device__ __forceinline__ float2 w16(int m) {
+  constexpr float c1 = 0.92387953251128674f, s1 = 0.38268343236508977f,
+                  c2 = 0.70710678118654752f;
+  switch (m & 15) {
+    case 0: return make_float2(1.f, 0.f);
+    case 1: return make_float2(c1, -s1);
+    case 2: return make_float2(c2, -c2);
+    case 3: return make_float2(s1, -c1);
+    case 4: return make_float2(0.f, -1.f);
+    case 5: return make_float2(-s1, -c1);
+    case 6: return make_float2(-c2, -c2);
+    case 7: return make_float2(-c1, -s1);
+    case 8: return make_float2(-1.f, 0.f);
+    case 9: return make_float2(-c1, s1);
+    case 10: return make_float2(-c2, c2);
+    case 11: return make_float2(-s1, c1);
+    case 12: return make_float2(0.f, 1.f);
+    case 13: return make_float2(s1, c1);
+    case 14: return make_float2(c2, c2);
+    default: return make_float2(c1, s1);
+  }
+}
+
+// 16-point DFT in place, natural order in and out (4 x 4 decomposition:
+// n = 4 n1 + n2, k = k1 + 4 k2).
+template <bool INV>
+__device__ __forceinline__ void dft16(float2 *v) {
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+  // v[n2 + 4 k1] now holds A[n2][k1]; apply W16^(n2 k1).
+#pragma unroll
+  for (int n2 = 1; n2 < 4; ++n2) {
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1) {
+      float2 w = w16(n2 * k1);
+      v[n2 + 4 * k1] = INV ? cmulc(v[n2 + 4 * k1], w) : cmul(v[n2 + 4 * k1], w);
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+    dft4<INV>(v[4 * k1 + 0], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+  // v[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4 x 4 index.
+  float2 t[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) t[i] = v[i];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[4 * k1 + k2];
+}
+
+// Twiddle from the 4096-entry table exp(-2 pi i n / 4096); INV conjugates.
+template <bool INV>
+__device__ __forceinline__ float2 twiddle(const float2 *__restrict__ tw,
+                                          int n) {
+  float2 w = tw[n & 4095];
+  return INV ? make_float2(w.x, -w.y) : w;
+}
+
+// v[r] *= w^r for r = 1..15, with w = table entry `idx` (powers formed by
+// repeated multiplication: one load and few live registers; the error
+// grows by about one ulp per power).
+template <bool INV>
+__device__ __forceinline__ void twiddle16(float2 *v,
+                                          const float2 *__restrict__ tw,
+                                          int idx) {
+  const float2 w = twiddle<INV>(tw, idx);
+  float2 cur = w;
+#pragma unroll
+  for (int r = 1; r < 16; ++r) {
+    v[r] = cmul(v[r], cur);
+    if (r < 15) cur = cmul(cur, w);
+  }
+}
+
+// Returns x unchanged but hides that from the optimiser, so that loads
+// indexed by it are not hoisted out of an enclosing loop (which would keep
+// tables of twiddles or taps live in registers across the whole loop).
+__device__ __forceinline__ int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// LDS index with one pad slot every 16 entries (spreads banks).
+__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
+
+}  // namespace lp

@@ -1,0 +1,109 @@
+// Internal declarations of liblp.so (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/lp.h"
+
+namespace lp {
+
+constexpr double kC = 299792458.0;  // speed of light, m/s
+constexpr int kM = LP_M;
+constexpr int kTaps = LP_TAPS;
+constexpr int kNfft = LP_NFFT;
+constexpr int kHop = LP_HOP;
+constexpr int kDelay = LP_DELAY;
+constexpr int kHist = kNfft - kHop;   // overlap-save history per series
+constexpr int kSynHist = 16;          // synthesis history frames kept
+constexpr int kTrigPerSeries = 256;   // triggers kept per (beam, trial)
+
+// Thread-local error reporting.
+lp_status set_error(lp_status code, const char *fmt, ...);
+lp_status hip_fail(hipError_t e, const char *what);
+
+#define LP_HIP(call)                                  \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return lp::hip_fail(e_, #call); \
+  } while (0)
+
+// Device buffer owned by the context.
+struct DevBuf {
+  void *p = nullptr;
+  size_t n = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  template <typename T>
+  T *as() const { return static_cast<T *>(p); }
+};
+
+// Beam-weight table for one (array, band, beam set, precision).
+struct BfPlan {
+  std::vector<uint8_t> key;
+  int prec = 0;
+  int n_in = 0, n_beams = 0, n_sb = 0;
+  int KS = 0, NT = 0;        // MFMA: k-steps of 16 real rows, n-tiles of 16
+  bool scaled = false;       // per-input power-of-two input scaling in use
+  DevBuf w;                  // FP16 MFMA fragments or FP32 [s][in][b]
+  DevBuf xscale;             // FP16 [KS*16] input scale factors (MFMA)
+};
+
+// Chirp constants for one (band, TEC list).
+struct DdPlan {
+  std::vector<uint8_t> key;
+  int n_tec = 0, n_sb = 0;
+  DevBuf base;   // f32 [J][S] frac(kappa T / f_k) in cycles
+  DevBuf afac;   // f32 [J][S] kappa T / f_k in cycles
+  DevBuf rfk;    // f32 [S] (subband rate / N_fft) / f_k
+};
+
+// Synthesis tables for one (band, prototype beta).
+struct SynPlan {
+  std::vector<uint8_t> key;
+  DevBuf taps;    // f32 [16][1024] g = M h
+  DevBuf binmap;  // i16 [512] subband position of bin k, or -1
+};
+
+}  // namespace lp
+
+struct lp_ctx {
+  int device = 0;
+  lp::DevBuf tw4096;  // float2 exp(-2 pi i n / 4096), n < 4096
+  std::mutex mu;
+  std::vector<std::unique_ptr<lp::BfPlan>> bf;
+  std::vector<std::unique_ptr<lp::DdPlan>> dd;
+  std::vector<std::unique_ptr<lp::SynPlan>> syn;
+};
+
+namespace lp {
+
+// Plan lookups (create on first use; creation is synchronous).
+lp_status get_bf_plan(lp_ctx *ctx, const lp_array *a, const lp_band *band,
+                      const lp_dir *beams, int n_beams, int prec,
+                      BfPlan **out);
+lp_status get_dd_plan(lp_ctx *ctx, const lp_band *band, const double *tec,
+                      int n_tec, DdPlan **out);
+lp_status get_syn_plan(lp_ctx *ctx, const lp_band *band, SynPlan **out);
+lp_status check_band(const lp_band *band);
+lp_status set_device(lp_ctx *ctx);
+
+// Remap a linear block index so that consecutive logical blocks land on the
+// same XCD (blocks are dealt round-robin over the 8 XCDs of the chip).
+__device__ inline long xcd_remap(long bid, long nblocks) {
+  const long nx = 8;
+  if (nblocks < nx * 2) return bid;
+  long per = nblocks / nx;           // full groups per XCD
+  long full = per * nx;
+  if (bid >= full) return bid;       // leftover tail keeps its index
+  return (bid % nx) * per + bid / nx;
+}
+
+}  // namespace lp

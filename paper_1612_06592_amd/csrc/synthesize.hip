@@ -1,0 +1,241 @@
+// Time-domain synthesis from the polyphase-filtered subbands (Winchen et
+// al. 2016, Sec. 2 and Sec. 3: the PPF inversion that recovers the 5 ns
+// signal), fused with the Hilbert envelope used by the trigger.
+//
+// Per series (beam, trial) and frame m:
+//   Z_m[n] = sum_k d_k[m] exp(+2 pi i k n / 1024)        (1024-point IFFT)
+//   z[1024 m + n] = sum_{t<16} g[1024 t + n] Z_{m-t}[n]   (polyphase FIR)
+// with g = M h.  Only positive bins are filled, so z is analytic: the real
+// series is 2 Re z and the envelope |2 z|.
+//
+// One 1024-thread workgroup per (series, block of F frames).  Frames are
+// transformed 16 at a time in a 139 KB LDS tile (radix 16, 16, 4 Stockham
+// passes, 64 threads per frame); thread n then owns FIR column n and keeps
+// Z_{m-15..m}[n] and its 16 taps in registers, so each output sample costs
+// 16 complex-by-real FMAs and nothing is written to HBM except the
+// per-frame envelope maximum (+ arg), per-16-frame sums of (2 Re z)^2 and,
+// on request, the real series.
+#include <cmath>
+
+#include "fft_dev.h"
+#include "lp_internal.h"
+
+namespace lp {
+
+constexpr int kSynThreads = 1024;
+constexpr int kSynFs = 1089;  // LDS frame stride (>= pad16(1023)+1, odd)
+
+struct SynCand {
+  float emax;
+  int arg;
+};
+
+__global__ __launch_bounds__(kSynThreads) void syn_kernel(
+    const float2 *__restrict__ d, float2 *__restrict__ hist,
+    const short *__restrict__ binmap, const float *__restrict__ taps,
+    const float2 *__restrict__ tw, float *__restrict__ x_out,
+    SynCand *__restrict__ cand, float *__restrict__ psum, int n_sb, long n_t,
+    long frame0, long warm, int F) {
+  __shared__ float2 lds[16 * kSynFs];
+  __shared__ float red_s[16];
+
+  const int series = blockIdx.y;
+  const long m0 = (long)blockIdx.x * F;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const float2 *ds = d + (long)series * n_sb * n_t;
+  float2 *hs = hist + (long)series * n_sb * kSynHist;
+
+  // FFT thread layout: frame f = tid % 16 (consecutive lanes read
+  // consecutive frames of one subband), butterfly j = tid / 16.
+  const int f = tid & 15, j = tid >> 4;
+  const int n = tid;  // FIR column
+
+  float2 win[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) win[t] = make_float2(0.f, 0.f);
+
+  const int n_chunk = F / 16;
+  for (int c = -1; c < n_chunk; ++c) {
+    const long mc = m0 + 16L * c;  // first frame of the chunk
+    // Per-chunk opaque copies of the thread indices keep address arithmetic
+    // inside the loop (hoisted, it would not fit in registers).
+    const int jo = opaque(j), no = opaque(n), fo = opaque(f);
+    const int lo = opaque(lane), wo = opaque(wave);
+    // ---- pass 0 (radix 16, Ns = 1): bins j + 64 r; bins >= 512 are empty.
+    float2 v[16];
+    {
+      const long m = mc + fo;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        int si = binmap[jo + 64 * r];
+        if (si >= 0)
+          v[r] = (m >= 0) ? ds[(long)si * n_t + m]
+                          : hs[si * kSynHist + (kSynHist + m)];
+      }
+    }
+    dft16<true>(v);
+    __syncthreads();  // previous chunk's FIR reads of lds are done
+    {
+      float2 *fr = lds + fo * kSynFs;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) fr[pad16(16 * jo + r)] = v[r];
+    }
+    __syncthreads();
+    if (c == -1 && m0 == 0) {
+      // Every history read of this block happened above: store the new
+      // history, the last 16 frames of d.
+      for (int i = tid; i < n_sb * kSynHist; i += kSynThreads) {
+        int si = i / kSynHist, fi = i % kSynHist;
+        hs[i] = ds[(long)si * n_t + (n_t - kSynHist + fi)];
+      }
+    }
+    // ---- pass 1 (radix 16, Ns = 16).
+    {
+      float2 *fr = lds + fo * kSynFs;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = fr[pad16(jo + 64 * r)];
+      twiddle16<true>(v, tw, (jo & 15) * 16);
+      dft16<true>(v);
+      __syncthreads();
+      int base = (jo >> 4) * 256 + (jo & 15);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) fr[pad16(base + 16 * r)] = v[r];
+    }
+    __syncthreads();
+    // ---- pass 2 (radix 4, Ns = 256): butterflies j + 64 q, q < 4; each
+    // reads and writes the same four slots, so no barrier in between.
+    {
+      float2 *fr = lds + fo * kSynFs;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int jj = jo + 64 * q, jt = jj;
+        float2 a0 = fr[pad16(jj)], a1 = fr[pad16(jj + 256)],
+               a2 = fr[pad16(jj + 512)], a3 = fr[pad16(jj + 768)];
+        const float2 w1 = twiddle<true>(tw, jt * 4), w2 = cmul(w1, w1);
+        a1 = cmul(a1, w1);
+        a2 = cmul(a2, w2);
+        a3 = cmul(a3, cmul(w2, w1));
+        dft4<true>(a0, a1, a2, a3);
+        fr[pad16(jj)] = a0;
+        fr[pad16(jj + 256)] = a1;
+        fr[pad16(jj + 512)] = a2;
+        fr[pad16(jj + 768)] = a3;
+      }
+    }
+    __syncthreads();
+    // ---- FIR, envelope, statistics for the 16 frames of this chunk.
+    if (c < 0) {
+#pragma unroll
+      for (int fi = 0; fi < 16; ++fi) win[fi] = lds[fi * kSynFs + pad16(no)];
+      continue;
+    }
+    // Taps are reloaded per chunk (cache hits) so they do not occupy
+    // registers during the transform.
+    float g[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) g[t] = taps[t * 1024 + no];
+    float acc_s = 0.f;
+    float *xo = x_out ? x_out + ((long)series * n_t + mc) * 1024 + no : nullptr;
+#pragma unroll
+    for (int fi = 0; fi < 16; ++fi) {
+      float2 *slot = lds + fi * kSynFs + pad16(no);
+      win[fi] = *slot;
+      float zr = 0.f, zi = 0.f;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        float2 w = win[(fi - t) & 15];
+        zr = fmaf(g[t], w.x, zr);
+        zi = fmaf(g[t], w.y, zi);
+      }
+      const float xr = 2.f * zr;
+      const bool valid = (frame0 + mc + fi) >= warm;
+      if (valid) acc_s = fmaf(xr, xr, acc_s);
+      if (xo) xo[(long)fi * 1024] = xr;
+      // The slot is consumed: reuse it for the squared envelope.
+      slot->x = 4.f * (zr * zr + zi * zi);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc_s += __shfl_xor(acc_s, off);
+    if (lo == 0) red_s[wo] = acc_s;
+    __syncthreads();
+    // Wave w finds the envelope maximum of frame w (lowest n on ties).
+    {
+      const float2 *fr = lds + wo * kSynFs;
+      float bv = -1.f;
+      int bi = 0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        int nn = lo + 64 * i;
+        float e2 = fr[pad16(nn)].x;
+        if (e2 > bv) {
+          bv = e2;
+          bi = nn;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        float ov = __shfl_xor(bv, off);
+        int oi = __shfl_xor(bi, off);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      if (lo == 0) {
+        SynCand o;
+        o.emax = sqrtf(bv);
+        o.arg = bi;
+        cand[(long)series * n_t + mc + wo] = o;
+      }
+    }
+    if (tid == 64) {
+      float sum = 0.f;
+      for (int w = 0; w < 16; ++w) sum += red_s[w];
+      psum[(long)series * (n_t / 16) + mc / 16] = sum;
+    }
+  }
+}
+
+}  // namespace lp
+
+using namespace lp;
+
+extern "C" lp_status lp_synthesize(lp_ctx *ctx, const lp_band *band,
+                                   const void *d, int32_t n_series,
+                                   int64_t n_t, int64_t frame0, void *hist,
+                                   float *x_out, void *cand,
+                                   void *hip_stream) {
+  if (!ctx || !d || !hist || !cand)
+    return set_error(LP_EINVAL, "lp_synthesize: NULL argument");
+  lp_status rc = check_band(band);
+  if (rc) return rc;
+  if (n_series <= 0 || n_series > 65535)
+    return set_error(LP_EINVAL, "lp_synthesize: n_series %d", n_series);
+  if (n_t <= 0 || n_t % kHop != 0)
+    return set_error(LP_EINVAL,
+                     "lp_synthesize: n_t %lld not a positive multiple of %d",
+                     (long long)n_t, kHop);
+  if (frame0 < 0) return set_error(LP_EINVAL, "lp_synthesize: frame0 < 0");
+  if ((rc = set_device(ctx))) return rc;
+  SynPlan *p = nullptr;
+  if ((rc = get_syn_plan(ctx, band, &p))) return rc;
+  // Frames per workgroup: long blocks amortise the 16-frame warm-up; short
+  // ones keep enough workgroups to fill the chip.
+  int F = 256;
+  while (F > 64 && (long)n_series * (n_t / F) < 1024) F /= 2;
+  const long n_wg = n_t / F;
+  char *cb = static_cast<char *>(cand);
+  SynCand *cd = reinterpret_cast<SynCand *>(cb);
+  float *ps = reinterpret_cast<float *>(cb + (size_t)n_series * n_t * 8);
+  hipLaunchKernelGGL(syn_kernel, dim3((unsigned)n_wg, n_series),
+                     dim3(kSynThreads), 0, static_cast<hipStream_t>(hip_stream),
+                     static_cast<const float2 *>(d), static_cast<float2 *>(hist),
+                     p->binmap.as<const short>(), p->taps.as<const float>(),
+                     ctx->tw4096.as<const float2>(), x_out, cd, ps, band->n_sb,
+                     (long)n_t, (long)frame0, (long)(kDelay + kTaps), F);
+  LP_HIP(hipGetLastError());
+  return LP_OK;
+}

@@ -1,0 +1,329 @@
+"""ctypes binding of liblp.so (see include/lp.h for the ABI).
+
+Argument marshalling only: every stage runs in the library's HIP kernels on
+the caller's stream.  torch supplies device memory and streams.  There is
+no CPU fallback: importing this module on a machine without the built
+library or without a GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblp.so")
+
+LP_OK, LP_EINVAL, LP_ENOMEM, LP_EAGAIN, LP_EHIP, LP_ECLOSED, LP_ETIMEOUT = (
+    0, -1, -2, -3, -4, -5, -6)
+LP_CI8, LP_CI16 = 1, 2
+LP_FP32, LP_FP16_MFMA = 0, 1
+LP_M, LP_TAPS, LP_NFFT, LP_HOP, LP_DELAY = 1024, 16, 4096, 2048, 1024
+LP_DD_KEEP_TAIL = 1
+WARM_FRAMES = LP_DELAY + LP_TAPS
+
+
+class LpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"liblp error {code}: {msg}")
+        self.code = code
+
+
+class lp_array(C.Structure):
+    _fields_ = [("n_st", C.c_int32), ("n_pol", C.c_int32),
+                ("enu_m", C.POINTER(C.c_double)),
+                ("gain", C.POINTER(C.c_float))]
+
+
+class lp_band(C.Structure):
+    _fields_ = [("n_sb", C.c_int32), ("k", C.POINTER(C.c_int32)),
+                ("f0_hz", C.c_double), ("fs_hz", C.c_double),
+                ("M", C.c_int32), ("taps", C.c_int32),
+                ("kaiser_beta", C.c_double)]
+
+
+class lp_dir(C.Structure):
+    _fields_ = [("az_rad", C.c_double), ("el_rad", C.c_double)]
+
+
+TRIG_DTYPE = np.dtype([("sample", np.int64), ("beam", np.int32),
+                       ("tec", np.int32), ("snr", np.float32),
+                       ("peak", np.float32)])
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run python -m paper_1612_06592_amd.build")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_float
+    L.lp_last_error.restype = C.c_char_p
+    L.lp_version.restype = C.c_char_p
+    L.lp_ctx_create.argtypes = [i32, C.POINTER(vp)]
+    L.lp_ctx_create.restype = i32
+    L.lp_ctx_destroy.argtypes = [vp]
+    L.lp_ctx_destroy.restype = None
+    for name, args in [("lp_beam_bytes", [i32, i32, i64]),
+                       ("lp_dd_state_bytes", [i32, i32]),
+                       ("lp_dd_bytes", [i32, i32, i32, i64]),
+                       ("lp_syn_state_bytes", [i32, i32]),
+                       ("lp_cand_bytes", [i32, i64]),
+                       ("lp_trigger_work_bytes", [i32, i32])]:
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_size_t
+    L.lp_beamform.argtypes = [vp, C.POINTER(lp_array), C.POINTER(lp_band),
+                              C.POINTER(lp_dir), i32, vp, i32, i64, i32, vp,
+                              vp]
+    L.lp_dedisperse.argtypes = [vp, C.POINTER(lp_band),
+                                C.POINTER(C.c_double), i32, vp, i32, i64, vp,
+                                i32, vp, vp]
+    L.lp_synthesize.argtypes = [vp, C.POINTER(lp_band), vp, i32, i64, i64,
+                                vp, vp, vp, vp]
+    L.lp_trigger.argtypes = [vp, vp, i32, i32, i64, i64, f32, vp, i32, vp,
+                             vp, vp, vp, vp, vp]
+    for name in ("lp_beamform", "lp_dedisperse", "lp_synthesize",
+                 "lp_trigger"):
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    """Names every build must export (those declared in include/lp.h)."""
+    return ["lp_last_error", "lp_version", "lp_ctx_create", "lp_ctx_destroy",
+            "lp_beam_bytes", "lp_dd_state_bytes", "lp_dd_bytes",
+            "lp_syn_state_bytes", "lp_cand_bytes", "lp_trigger_work_bytes",
+            "lp_beamform", "lp_dedisperse", "lp_synthesize", "lp_trigger"]
+
+
+def check(rc: int):
+    if rc != LP_OK:
+        raise LpError(rc, lib().lp_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# ----------------------------------------------------------- descriptors
+
+class Array:
+    """Station array descriptor (keeps its host buffers alive)."""
+
+    def __init__(self, enu, n_pol: int = 2, gain=None):
+        self.enu = np.ascontiguousarray(enu, dtype=np.float64)
+        self.gain = None if gain is None else np.ascontiguousarray(gain, np.float32)
+        self.n_pol = n_pol
+        self.c = lp_array(self.enu.shape[0], n_pol,
+                          self.enu.ctypes.data_as(C.POINTER(C.c_double)),
+                          None if self.gain is None else
+                          self.gain.ctypes.data_as(C.POINTER(C.c_float)))
+
+    @property
+    def n_in(self) -> int:
+        return self.enu.shape[0] * self.n_pol
+
+
+class Band:
+    def __init__(self, k, f0: float = 100e6, fs: float = 200e6,
+                 beta: float = 9.0):
+        self.k = np.ascontiguousarray(k, dtype=np.int32)
+        self.c = lp_band(len(self.k),
+                         self.k.ctypes.data_as(C.POINTER(C.c_int32)), f0, fs,
+                         LP_M, LP_TAPS, beta)
+
+    @property
+    def n_sb(self) -> int:
+        return len(self.k)
+
+
+class Dirs:
+    def __init__(self, az_el):
+        a = np.ascontiguousarray(az_el, dtype=np.float64).reshape(-1, 2)
+        self.arr = (lp_dir * len(a))(*[lp_dir(float(x), float(y)) for x, y in a])
+        self.n = len(a)
+
+
+class Ctx:
+    def __init__(self, device: int = 0):
+        self.h = C.c_void_p()
+        check(lib().lp_ctx_create(device, C.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            lib().lp_ctx_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- stages
+
+def beamform(ctx: Ctx, array: Array, band: Band, dirs: Dirs, x, n_t: int,
+             dtype: int, prec: int, y, stream=None):
+    check(lib().lp_beamform(ctx.h, C.byref(array.c), C.byref(band.c),
+                            dirs.arr, dirs.n, _ptr(x), dtype, n_t, prec,
+                            _ptr(y), _stream(stream)))
+
+
+def dedisperse(ctx: Ctx, band: Band, tec, y, n_beams: int, n_t: int, tail, d,
+               flags: int = 0, stream=None):
+    t = np.ascontiguousarray(np.atleast_1d(tec), dtype=np.float64)
+    check(lib().lp_dedisperse(ctx.h, C.byref(band.c),
+                              t.ctypes.data_as(C.POINTER(C.c_double)), len(t),
+                              _ptr(y), n_beams, n_t, _ptr(tail), flags,
+                              _ptr(d), _stream(stream)))
+
+
+def synthesize(ctx: Ctx, band: Band, d, n_series: int, n_t: int, frame0: int,
+               hist, cand, x_out=None, stream=None):
+    check(lib().lp_synthesize(ctx.h, C.byref(band.c), _ptr(d), n_series, n_t,
+                              frame0, _ptr(hist), _ptr(x_out), _ptr(cand),
+                              _stream(stream)))
+
+
+def trigger(ctx: Ctx, cand, n_beams: int, n_tec: int, n_t: int, frame0: int,
+            k_sigma: float, out, cap: int, n_out, work, snr_out=None,
+            best_tec=None, sigma_out=None, stream=None):
+    check(lib().lp_trigger(ctx.h, _ptr(cand), n_beams, n_tec, n_t, frame0,
+                           k_sigma, _ptr(out), cap, _ptr(n_out),
+                           _ptr(snr_out), _ptr(best_tec), _ptr(sigma_out),
+                           _ptr(work), _stream(stream)))
+
+
+def nbytes(name: str, *args) -> int:
+    return int(getattr(lib(), name)(*args))
+
+
+# ------------------------------------------------------ stream pipeline
+
+@dataclass
+class Pipeline:
+    """Device buffers and carried state for one observation stream, and the
+    four-stage chain per block.  Buffers are torch tensors on `device`."""
+
+    ctx: Ctx
+    array: Array
+    band: Band
+    dirs: Dirs
+    tec: np.ndarray
+    n_t: int
+    dtype: int = LP_CI8
+    prec: int = LP_FP16_MFMA
+    k_sigma: float = 6.0
+    trig_cap: int = 4096
+    want_series: bool = False
+    device: str = "cuda:0"
+    frame0: int = 0
+    bufs: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        import torch
+        self.tec = np.atleast_1d(np.asarray(self.tec, dtype=np.float64))
+        B, S, J, n_t = self.dirs.n, self.band.n_sb, len(self.tec), self.n_t
+        u8 = dict(dtype=torch.uint8, device=self.device)
+
+        def buf(n):
+            return torch.empty(n, **u8)
+
+        self.bufs = dict(
+            y=buf(nbytes("lp_beam_bytes", B, S, n_t)),
+            d=buf(nbytes("lp_dd_bytes", B, J, S, n_t)),
+            tail=torch.zeros(nbytes("lp_dd_state_bytes", B, S), **u8),
+            hist=torch.zeros(nbytes("lp_syn_state_bytes", B * J, S), **u8),
+            cand=buf(nbytes("lp_cand_bytes", B * J, n_t)),
+            work=buf(nbytes("lp_trigger_work_bytes", B, J)),
+            trig=torch.zeros(self.trig_cap * TRIG_DTYPE.itemsize, **u8),
+            n_trig=torch.zeros(1, dtype=torch.int32, device=self.device),
+            snr=torch.zeros((B, J), dtype=torch.float32, device=self.device),
+            best=torch.zeros(B, dtype=torch.int32, device=self.device),
+            sigma=torch.zeros((B, J), dtype=torch.float32, device=self.device),
+        )
+        if self.want_series:
+            self.bufs["x_out"] = torch.empty((B * J, n_t * LP_M),
+                                             dtype=torch.float32,
+                                             device=self.device)
+
+    @property
+    def n_beams(self):
+        return self.dirs.n
+
+    @property
+    def n_tec(self):
+        return len(self.tec)
+
+    def beamform(self, x, stream=None):
+        beamform(self.ctx, self.array, self.band, self.dirs, x, self.n_t,
+                 self.dtype, self.prec, self.bufs["y"], stream)
+
+    def dedisperse(self, stream=None):
+        dedisperse(self.ctx, self.band, self.tec, self.bufs["y"],
+                   self.n_beams, self.n_t, self.bufs["tail"], self.bufs["d"],
+                   0, stream)
+
+    def synthesize(self, stream=None):
+        synthesize(self.ctx, self.band, self.bufs["d"],
+                   self.n_beams * self.n_tec, self.n_t, self.frame0,
+                   self.bufs["hist"], self.bufs["cand"],
+                   self.bufs.get("x_out"), stream)
+
+    def trigger(self, stream=None):
+        b = self.bufs
+        trigger(self.ctx, b["cand"], self.n_beams, self.n_tec, self.n_t,
+                self.frame0, self.k_sigma, b["trig"], self.trig_cap,
+                b["n_trig"], b["work"], b["snr"], b["best"], b["sigma"],
+                stream)
+
+    def step(self, x, stream=None):
+        """Whole chain on one block (asynchronous); advances the stream."""
+        self.beamform(x, stream)
+        self.dedisperse(stream)
+        self.synthesize(stream)
+        self.trigger(stream)
+        self.frame0 += self.n_t
+
+    def triggers(self) -> np.ndarray:
+        n = int(self.bufs["n_trig"].item())
+        raw = self.bufs["trig"][: min(n, self.trig_cap) * TRIG_DTYPE.itemsize]
+        return raw.cpu().numpy().view(TRIG_DTYPE).copy()
+
+    # views of the intermediate device buffers
+    def y_view(self):
+        import torch
+        B, S = self.n_beams, self.band.n_sb
+        return self.bufs["y"].view(torch.float32).view(B, S, self.n_t, 2)
+
+    def d_view(self):
+        import torch
+        B, J, S = self.n_beams, self.n_tec, self.band.n_sb
+        return self.bufs["d"].view(torch.float32).view(B, J, S, self.n_t, 2)
+
+    def cand_view(self):
+        """(emax [ns][n_t] f32, arg [ns][n_t] i32, psum [ns][n_t/16] f32)."""
+        import torch
+        ns, n_t = self.n_beams * self.n_tec, self.n_t
+        c = self.bufs["cand"]
+        head = c[: ns * n_t * 8].view(torch.int32).view(ns, n_t, 2)
+        emax = head[..., 0].view(torch.float32)
+        arg = head[..., 1]
+        psum = c[ns * n_t * 8: ns * n_t * 8 + ns * (n_t // 16) * 4].view(
+            torch.float32).view(ns, n_t // 16)
+        return emax, arg, psum

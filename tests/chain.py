@@ -1,0 +1,143 @@
+"""Helpers shared by the GPU tests: run the HIP chain through the C ABI and
+the FP64 oracle chain on the same generated block, and compare them.
+
+The oracle is run in memory-bounded pieces (subband groups for the
+beamformer, series groups for synthesis), which changes nothing in its
+arithmetic: every unit it computes is independent."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from paper_1612_06592_amd import lp
+
+M = 1024
+WARM = lp.WARM_FRAMES
+
+
+def rel_rms(a, b) -> float:
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.sqrt(np.sum(np.abs(a - b) ** 2) / np.sum(np.abs(b) ** 2)))
+
+
+def as_complex(t):
+    a = t.detach().cpu().numpy()
+    return a[..., 0].astype(np.float64) + 1j * a[..., 1].astype(np.float64)
+
+
+def gpu_pipeline(blk, prec, n_t=None, want_series=True, tec=None, device="cuda:0"):
+    n_t = n_t or blk.n_t
+    ctx = lp.Ctx(0)
+    p = lp.Pipeline(ctx, lp.Array(blk.enu, 2), lp.Band(blk.k), lp.Dirs(blk.az_el),
+                    blk.tec if tec is None else tec, n_t,
+                    dtype=lp.LP_CI8 if blk.x.dtype == np.int8 else lp.LP_CI16,
+                    prec=prec, want_series=want_series, device=device)
+    return ctx, p
+
+
+def to_device(x, device="cuda:0"):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device)
+
+
+def run_gpu(blk, prec, want_series=True, blocks=None):
+    """Run the chain over consecutive blocks (default: the whole block)."""
+    import torch
+    ctx, p = gpu_pipeline(blk, prec, n_t=blocks or blk.n_t,
+                          want_series=want_series)
+    xs = [blk.x] if blocks is None else [
+        blk.x[:, i:i + blocks] for i in range(0, blk.n_t, blocks)]
+    outs = []
+    for x in xs:
+        xd = to_device(x)
+        p.step(xd)
+        torch.cuda.synchronize()
+        emax, arg, psum = p.cand_view()
+        outs.append(dict(
+            y=as_complex(p.y_view()), d=as_complex(p.d_view()),
+            x=(p.bufs["x_out"].cpu().numpy() if want_series else None),
+            emax=emax.cpu().numpy(), arg=arg.cpu().numpy(),
+            sigma=p.bufs["sigma"].cpu().numpy(), snr=p.bufs["snr"].cpu().numpy(),
+            best=p.bufs["best"].cpu().numpy(), trig=p.triggers(),
+            n_trig=int(p.bufs["n_trig"].item())))
+    ctx.close()
+    return outs if blocks is not None else outs[0]
+
+
+class OracleChain:
+    """The oracle's chain over consecutive blocks, memory-bounded."""
+
+    def __init__(self, blk, tec=None, sb_group=32, series_group=8):
+        self.blk = blk
+        self.tec = np.atleast_1d(blk.tec if tec is None else tec).astype(float)
+        B, S, J = blk.az_el.shape[0], len(blk.k), len(self.tec)
+        self.h = oracle.prototype(M, 16, 9.0)
+        self.tail = np.zeros((B, S, 2048), complex)
+        self.hist = np.zeros((B * J, 15, S), complex)
+        self.frame0 = 0
+        self.sb_group = sb_group
+        self.series_group = series_group
+
+    def process(self, x, keep_series=()):
+        blk = self.blk
+        B, S, J = blk.az_el.shape[0], len(blk.k), len(self.tec)
+        n_t = x.shape[1]
+        y = np.zeros((B, S, n_t), complex)
+        for s0 in range(0, S, self.sb_group):
+            s1 = min(S, s0 + self.sb_group)
+            y[:, s0:s1] = oracle.beamform(blk.enu, 2, blk.k[s0:s1], blk.az_el,
+                                          x[s0:s1])
+        d = oracle.dedisperse(blk.k, self.tec, y, self.tail)
+        dq = d.reshape(B * J, S, n_t)
+        sigma = np.zeros(B * J)
+        wmax = np.zeros((B * J, n_t))
+        warg = np.zeros((B * J, n_t), np.int64)
+        series = {}
+        for q0 in range(0, B * J, self.series_group):
+            q1 = min(B * J, q0 + self.series_group)
+            hq = self.hist[q0:q1].copy()
+            z = oracle.synthesize(self.h, blk.k, dq[q0:q1], hq)
+            self.hist[q0:q1] = hq
+            s_, w_, a_ = oracle.detect(z, n_t, self.frame0, WARM)
+            sigma[q0:q1], wmax[q0:q1], warg[q0:q1] = s_, w_, a_
+            for q in keep_series:
+                if q0 <= q < q1:
+                    series[q] = z[q - q0]
+        trig, snr, best = oracle.trigger(sigma, wmax, warg, B, J, n_t,
+                                         self.frame0, WARM)
+        self.frame0 += n_t
+        return dict(y=y, d=d, z=series, sigma=sigma, wmax=wmax, warg=warg,
+                    trig=trig, snr=snr, best=best)
+
+
+def compare_triggers(g, o, sigma_o, tol_idx=1, border=0.01):
+    """Trigger lists must agree (beam exact, sample +-tol_idx), except for
+    oracle or GPU triggers whose SNR lies within `border` (relative) of the
+    threshold 6: those decisions are taken on values that differ by the
+    stated rounding error and may flip."""
+    def key(t):
+        return int(t["beam"]), int(t["sample"])
+
+    gl = [t for t in g]
+    ol = [t for t in o]
+    used = set()
+    missing = []
+    for t in ol:
+        b, s = key(t)
+        hit = None
+        for i, u in enumerate(gl):
+            if i in used:
+                continue
+            if int(u["beam"]) == b and abs(int(u["sample"]) - s) <= tol_idx:
+                hit = i
+                break
+        if hit is None:
+            if abs(t["snr"] / 6.0 - 1.0) > border:
+                missing.append((b, s, float(t["snr"])))
+        else:
+            used.add(hit)
+    extra = [(int(u["beam"]), int(u["sample"]), float(u["snr"]))
+             for i, u in enumerate(gl)
+             if i not in used and abs(u["snr"] / 6.0 - 1.0) > border]
+    return missing, extra

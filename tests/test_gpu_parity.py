@@ -1,0 +1,195 @@
+"""GPU parity: the HIP chain (through the C ABI) against the FP64 oracle on
+the same seeded blocks.
+
+Tolerances (relative RMS over each stage's whole output):
+  FP16-MFMA beamformer path: 1e-3 (the target bound); FP32 path: 1e-5.
+Triggers: beam exact and sample within +-1, except decisions within 1% of
+the 6-sigma threshold (see chain.compare_triggers).  Window maxima are
+compared in value; their positions must agree except where the oracle's
+own envelope at the GPU's position is within 1e-3 of its maximum.
+"""
+import numpy as np
+import pytest
+
+import lofarsim
+from chain import OracleChain, compare_triggers, rel_rms, run_gpu
+from paper_1612_06592_amd import lp
+
+pytestmark = pytest.mark.gpu
+
+TOL = {lp.LP_FP16_MFMA: 1e-3, lp.LP_FP32: 1e-5}
+
+
+def _check_block(g, o, prec, keep=(0,), label=""):
+    tol = TOL[prec]
+    e = rel_rms(g["y"], o["y"])
+    print(f"{label} y rel-rms {e:.2e}", flush=True)
+    assert e <= tol
+    e = rel_rms(g["d"], o["d"])
+    print(f"{label} d rel-rms {e:.2e}", flush=True)
+    assert e <= tol
+    for q in keep:
+        if g["x"] is not None and q in o["z"]:
+            e = rel_rms(g["x"][q], 2 * o["z"][q].real)
+            print(f"{label} x[{q}] rel-rms {e:.2e}", flush=True)
+            assert e <= tol
+    ns, n_t = o["wmax"].shape
+    e = rel_rms(g["emax"], o["wmax"])
+    assert e <= tol, e
+    gs = g["sigma"].reshape(-1)
+    assert np.max(np.abs(gs - o["sigma"]) / np.maximum(o["sigma"], 1e-30)) <= tol
+    # Window arg-max: equal, or an equally good sample of the oracle.
+    for q in keep:
+        if q not in o["z"]:
+            continue
+        env = np.abs(2 * o["z"][q]).reshape(n_t, 1024)
+        ga = g["arg"][q]
+        oa = o["warg"][q] % 1024
+        bad = np.nonzero(ga != oa)[0]
+        for m in bad:
+            assert env[m, ga[m]] >= (1 - 1e-3) * env[m, oa[m]], (q, m)
+        assert len(bad) <= max(2, n_t // 100)
+    miss, extra = compare_triggers(g["trig"], o["trig"], o["sigma"])
+    print(f"{label} triggers gpu={len(g['trig'])} oracle={len(o['trig'])}",
+          flush=True)
+    assert not miss and not extra, (miss, extra)
+    assert g["n_trig"] == len(g["trig"])
+    assert np.array_equal(g["best"], o["best"])
+    assert np.max(np.abs(g["snr"].reshape(-1) - o["snr"].reshape(-1))
+                  / np.maximum(o["snr"].reshape(-1), 1e-30)) <= 2 * tol
+
+
+@pytest.mark.parametrize("prec", [lp.LP_FP32, lp.LP_FP16_MFMA])
+def test_c1_tiny_full(prec):
+    blk = lofarsim.generate(lofarsim.get_config("c1"))
+    print("case c1", prec, flush=True)
+    g = run_gpu(blk, prec)
+    o = OracleChain(blk).process(blk.x, keep_series=(0,))
+    _check_block(g, o, prec, label=f"c1 prec={prec}")
+    # The injected pulse is found.
+    assert any(abs(int(t["sample"]) - blk.pulses[0]["n0"]) <= 1 for t in g["trig"])
+
+
+@pytest.mark.parametrize("prec", [lp.LP_FP32, lp.LP_FP16_MFMA])
+def test_c2_slice_core_single_beam(prec):
+    cfg = lofarsim.get_config("c2", n_t=4096, n_pulses=1)
+    blk = lofarsim.generate(cfg)
+    print("case c2-slice", prec, flush=True)
+    g = run_gpu(blk, prec)
+    o = OracleChain(blk).process(blk.x, keep_series=(0,))
+    _check_block(g, o, prec, label=f"c2s prec={prec}")
+
+
+def test_c3_slice_multibeam_19():
+    cfg = lofarsim.get_config("c3", n_t=4096, hex_rings=2,
+                              k=tuple(range(52, 76)))
+    blk = lofarsim.generate(cfg)
+    print("case c3-slice 19 beams", flush=True)
+    g = run_gpu(blk, lp.LP_FP16_MFMA)
+    o = OracleChain(blk).process(blk.x, keep_series=(0, 5, 18))
+    _check_block(g, o, lp.LP_FP16_MFMA, keep=(0, 5, 18), label="c3s")
+
+
+def test_beamform_61_beams_96_inputs():
+    """C3's GEMM shape (96 inputs x 61 beams): two n-tiles per wave."""
+    cfg = lofarsim.get_config("c3", n_t=2048, k=tuple(range(52, 84)))
+    blk = lofarsim.generate(cfg)
+    import oracle
+    import torch
+    from chain import as_complex, gpu_pipeline, to_device
+    for prec in (lp.LP_FP16_MFMA, lp.LP_FP32):
+        ctx, p = gpu_pipeline(blk, prec, want_series=False)
+        p.beamform(to_device(blk.x))
+        torch.cuda.synchronize()
+        y = as_complex(p.y_view())
+        ctx.close()
+        ref = oracle.beamform(blk.enu, 2, blk.k, blk.az_el, blk.x)
+        e = rel_rms(y, ref)
+        print("bf61 prec", prec, "rel-rms", e, flush=True)
+        assert e <= TOL[prec]
+
+
+def test_c4_slice_tec_grid():
+    tec = tuple(np.linspace(0, 30, 32).tolist())
+    cfg = lofarsim.get_config("c4", n_t=2048, k=tuple(range(52, 68)),
+                              n_pulses=1, snr=(30.0, 30.0))
+    blk = lofarsim.generate(cfg)
+    print("case c4-slice", cfg.true_tec_index, flush=True)
+    g = run_gpu(blk, lp.LP_FP16_MFMA)
+    keep = (0, cfg.true_tec_index, 6 * 32 + 31)
+    o = OracleChain(blk).process(blk.x, keep_series=keep)
+    _check_block(g, o, lp.LP_FP16_MFMA, keep=keep, label="c4s")
+
+
+def test_odd_shapes_and_ci16_mfma():
+    """Inputs not a multiple of 16 real rows (6 stations), 3 beams, int16
+    samples on the MFMA path, a single hop."""
+    cfg = lofarsim.get_config("c1", n_st=6, hex_rings=0, n_t=2048,
+                              k=tuple(range(300, 311)))
+    blk = lofarsim.generate(cfg)
+    blk.az_el = np.concatenate([blk.az_el, blk.az_el + 0.002,
+                                blk.az_el - 0.003])
+    for prec in (lp.LP_FP16_MFMA, lp.LP_FP32):
+        g = run_gpu(blk, prec)
+        o = OracleChain(blk).process(blk.x, keep_series=(0, 2))
+        _check_block(g, o, prec, keep=(0, 2), label=f"odd prec={prec}")
+
+
+def test_stream_state_carry_bitwise():
+    """Two consecutive blocks through carried state equal one long block
+    (bitwise for every sample-local output)."""
+    cfg = lofarsim.get_config("c2", n_t=8192, k=tuple(range(52, 84)),
+                              n_pulses=1)
+    blk = lofarsim.generate(cfg)
+    one = run_gpu(blk, lp.LP_FP16_MFMA)
+    two = run_gpu(blk, lp.LP_FP16_MFMA, blocks=4096)
+    assert np.array_equal(np.concatenate([two[0]["d"], two[1]["d"]], -1),
+                          one["d"])
+    assert np.array_equal(np.concatenate([two[0]["x"], two[1]["x"]], -1),
+                          one["x"])
+    assert np.array_equal(np.concatenate([two[0]["emax"], two[1]["emax"]], -1),
+                          one["emax"])
+    # And both match the oracle run the same way.
+    oc = OracleChain(blk)
+    o1 = oc.process(blk.x[:, :4096], keep_series=(0,))
+    o2 = oc.process(blk.x[:, 4096:], keep_series=(0,))
+    assert rel_rms(two[1]["x"][0], 2 * o2["z"][0].real) <= 1e-3
+    miss, extra = compare_triggers(two[1]["trig"], o2["trig"], o2["sigma"])
+    assert not miss and not extra
+
+
+def test_determinism_bitwise():
+    cfg = lofarsim.get_config("c2", n_t=4096, k=tuple(range(52, 100)))
+    blk = lofarsim.generate(cfg)
+    a = run_gpu(blk, lp.LP_FP16_MFMA)
+    b = run_gpu(blk, lp.LP_FP16_MFMA)
+    for k in ("y", "d", "x", "emax", "arg", "sigma", "snr"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["trig"], b["trig"])
+
+
+def test_invalid_arguments_rejected():
+    import torch
+    from chain import gpu_pipeline
+    blk = lofarsim.generate(lofarsim.get_config("c1"))
+    ctx, p = gpu_pipeline(blk, lp.LP_FP16_MFMA)
+    x = torch.zeros(8, device="cuda:0", dtype=torch.int8)
+    with pytest.raises(lp.LpError) as e:
+        lp.beamform(ctx, p.array, p.band, p.dirs, x, 100, lp.LP_CI16,
+                    lp.LP_FP16_MFMA, p.bufs["y"])
+    assert e.value.code == lp.LP_EINVAL
+    with pytest.raises(lp.LpError):
+        lp.dedisperse(ctx, p.band, [5.0], p.bufs["y"], 1, 3000,
+                      p.bufs["tail"], p.bufs["d"])
+    with pytest.raises(lp.LpError):
+        lp.dedisperse(ctx, p.band, [-1.0], p.bufs["y"], 1, 4096,
+                      p.bufs["tail"], p.bufs["d"])
+    many = lp.Dirs(np.tile(blk.az_el, (65, 1)))
+    with pytest.raises(lp.LpError):
+        lp.beamform(ctx, p.array, p.band, many, x, 4096, lp.LP_CI16,
+                    lp.LP_FP16_MFMA, p.bufs["y"])
+    bad = lp.Band([5, 5, 6])
+    with pytest.raises(lp.LpError):
+        lp.synthesize(ctx, bad, p.bufs["d"], 1, 4096, 0, p.bufs["hist"],
+                      p.bufs["cand"])
+    ctx.close()
