@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import lofarsim
-from chain import OracleChain, compare_triggers, rel_rms, run_gpu
+from chain import WARM, OracleChain, compare_triggers, rel_rms, run_gpu
 from paper_1612_06592_amd import lp
 
 pytestmark = pytest.mark.gpu
@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 TOL = {lp.LP_FP16_MFMA: 1e-3, lp.LP_FP32: 1e-5}
 
 
-def _check_block(g, o, prec, keep=(0,), label=""):
+def _check_block(g, o, prec, keep=(0,), label="", frame0=0):
     tol = TOL[prec]
     e = rel_rms(g["y"], o["y"])
     print(f"{label} y rel-rms {e:.2e}", flush=True)
@@ -35,17 +35,21 @@ def _check_block(g, o, prec, keep=(0,), label=""):
             assert e <= tol
     ns, n_t = o["wmax"].shape
     e = rel_rms(g["emax"], o["wmax"])
+    print(f"{label} window-max rel-rms {e:.2e}", flush=True)
     assert e <= tol, e
     gs = g["sigma"].reshape(-1)
     assert np.max(np.abs(gs - o["sigma"]) / np.maximum(o["sigma"], 1e-30)) <= tol
-    # Window arg-max: equal, or an equally good sample of the oracle.
+    # Window arg-max over valid frames (start-up frames of a fresh stream
+    # are numerically zero on both sides): equal, or an equally good
+    # sample of the oracle.
+    first = max(0, WARM - frame0)
     for q in keep:
         if q not in o["z"]:
             continue
         env = np.abs(2 * o["z"][q]).reshape(n_t, 1024)
         ga = g["arg"][q]
         oa = o["warg"][q] % 1024
-        bad = np.nonzero(ga != oa)[0]
+        bad = [m for m in np.nonzero(ga != oa)[0] if m >= first]
         for m in bad:
             assert env[m, ga[m]] >= (1 - 1e-3) * env[m, oa[m]], (q, m)
         assert len(bad) <= max(2, n_t // 100)
