@@ -59,8 +59,11 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--prec", default="fp16", choices=["fp16", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-hops", type=int, default=8,
+    ap.add_argument("--cpu-hops", type=int, default=32,
                     help="hops (2048 samples each) in the oracle sample")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (for "
+                         "calibrating HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (the hot path "
@@ -88,6 +91,14 @@ def main():
                     dtype=lp.LP_CI8 if cfg.dtype == "ci8" else lp.LP_CI16,
                     prec=prec, want_series=False, device=dev)
     stream = torch.cuda.current_stream()
+    if a.calib_copy_mib:
+        n = a.calib_copy_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(a.warmup):
         p.step(x)
     torch.cuda.synchronize()

@@ -148,15 +148,22 @@ def beamform(enu, n_pol: int, k, az_el, x, f0: float = 100e6,
     n_st = enu.shape[0]
     k = np.ascontiguousarray(k, dtype=np.int32)
     az_el = np.ascontiguousarray(az_el, dtype=np.float64).reshape(-1, 2)
-    x = np.ascontiguousarray(x, dtype=np.float64)
     n_sb, n_t = x.shape[0], x.shape[1]
     assert x.shape[2] == n_st * n_pol and x.shape[3] == 2
     g = None if gain is None else np.ascontiguousarray(gain, np.float64)
     y = np.zeros((az_el.shape[0], n_sb, n_t), dtype=np.complex128)
-    lib().lpo_beamform(n_st, n_pol, _dp(enu), None if g is None else _dp(g),
-                       n_sb, _ip(k), f0, fs, M, az_el.shape[0], _dp(az_el),
-                       n_t, _dp(x),
-                       _dp(y.view(np.float64)))
+    # Subbands are independent: convert and sum a few at a time so a large
+    # integer block is never held whole in FP64.
+    step = max(1, (1 << 27) // max(1, n_t * n_st * n_pol * 2))
+    for s0 in range(0, n_sb, step):
+        s1 = min(n_sb, s0 + step)
+        xs = np.ascontiguousarray(x[s0:s1], dtype=np.float64)
+        ys = np.zeros((az_el.shape[0], s1 - s0, n_t), dtype=np.complex128)
+        lib().lpo_beamform(n_st, n_pol, _dp(enu),
+                           None if g is None else _dp(g), s1 - s0,
+                           _ip(k[s0:s1]), f0, fs, M, az_el.shape[0],
+                           _dp(az_el), n_t, _dp(xs), _dp(ys.view(np.float64)))
+        y[:, s0:s1] = ys
     return y
 
 
