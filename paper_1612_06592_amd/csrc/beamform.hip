@@ -107,88 +107,143 @@ __device__ __forceinline__ void load_vec(T *dst, const char *src) {
   }
 }
 
-template <typename IT, int VB>
-__device__ inline void stage_tile_f16(const IT *__restrict__ src, int RK,
-                                      int RKP, int KS,
-                                      const _Float16 *__restrict__ xscale,
-                                      bool scaled, _Float16 *__restrict__ sm) {
-  constexpr int EPV = VB / (int)sizeof(IT);  // elements per vector
-  const int nvec = kBfT * RK / EPV;
-  const char *base = reinterpret_cast<const char *>(src);
-  for (int v = threadIdx.x; v < nvec; v += kBfThreads) {
-    int e0 = v * EPV;
-    int row = e0 / RK, col = e0 - row * RK;
-    IT raw[EPV];
-    load_vec<VB>(raw, base + (size_t)v * VB);
-    _Float16 hv[EPV];
-#pragma unroll
-    for (int i = 0; i < EPV; ++i) {
-      _Float16 h = (_Float16)(float)raw[i];
-      hv[i] = scaled ? h * xscale[col + i] : h;
-    }
-    _Float16 *dst = sm + row * RKP + col;
-    if constexpr (EPV % 8 == 0) {
-#pragma unroll
-      for (int i = 0; i < EPV; i += 8) {
-        int4 q;
-        __builtin_memcpy(&q, hv + i, 16);
-        *reinterpret_cast<int4 *>(dst + i) = q;
-      }
-    } else if constexpr (EPV == 4) {
-      int2 q;
-      __builtin_memcpy(&q, hv, 8);
-      *reinterpret_cast<int2 *>(dst) = q;
-    } else {
-      int q;
-      __builtin_memcpy(&q, hv, 4);
-      *reinterpret_cast<int *>(dst) = q;
-    }
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+// Exact int -> FP16 of one 32-bit word: four int8 (as two half2) or two
+// int16 (one half2).  For int8 the biased byte u = x + 128 is placed under
+// the FP16 exponent of 1024 (bit pattern 0x6400 | u, value 1024 + u, exact
+// since the FP16 ulp at 1024 is 1) and 1152 is subtracted.
+template <typename IT>
+__device__ __forceinline__ int word_to_half2(unsigned w, half2v *out) {
+  if constexpr (sizeof(IT) == 1) {
+    unsigned u = w ^ 0x80808080u;
+    unsigned lo = __builtin_amdgcn_perm(u, 0x64646464u, 0x00050004u);
+    unsigned hi = __builtin_amdgcn_perm(u, 0x64646464u, 0x00070006u);
+    half2v a, b;
+    __builtin_memcpy(&a, &lo, 4);
+    __builtin_memcpy(&b, &hi, 4);
+    const half2v off = {(_Float16)1152.0f, (_Float16)1152.0f};
+    out[0] = a - off;
+    out[1] = b - off;
+    return 2;
+  } else {
+    half2v a;
+    a[0] = (_Float16)(short)(w & 0xffffu);
+    a[1] = (_Float16)(short)(w >> 16);
+    out[0] = a;
+    return 1;
   }
-  // Zero the columns RK .. KS*16-1 (their weights are zero too, but stale
-  // LDS could hold NaN bit patterns).
-  int padc = KS * 16 - RK;
-  if (padc > 0)
-    for (int i = threadIdx.x; i < kBfT * padc; i += kBfThreads)
-      sm[(i / padc) * RKP + RK + (i % padc)] = (_Float16)0.0f;
 }
 
-// Grid: x = time-tile groups, y = subband.  Waves are laid out WM x WN over
-// (16-row m-tiles, 16-column n-tiles); each wave keeps its NPW n-tiles of
-// weight fragments in registers for all of its tiles.
-template <typename IT, int VB, int NPW>
+typedef int intx4 __attribute__((ext_vector_type(4)));
+typedef int intx2 __attribute__((ext_vector_type(2)));
+template <int VB> struct VecT;
+template <> struct VecT<16> { typedef intx4 type; };
+template <> struct VecT<8> { typedef intx2 type; };
+template <> struct VecT<4> { typedef int type; };
+
+// Grid: x = groups of tiles (T time rows each), y = subband.  Waves are laid
+// out WM x WN over (16-row m-tiles, 16-column n-tiles); each wave keeps its
+// NPW n-tiles of weight fragments in registers for all of its tiles.  The
+// next tile's input is loaded into registers while the current tile is
+// multiplied and stored (up to 128 bytes per thread in flight).
+template <typename IT, int VB, int NPW, int KSM>
 __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
     const IT *__restrict__ x, const half4 *__restrict__ wf,
     const _Float16 *__restrict__ xscale, int scaled, float2 *__restrict__ y,
-    int n_sb, long n_t, int RK, int KS, int NT, int WN, int n_beams,
+    int n_sb, long n_t, int RK, int KS, int NT, int WN, int n_beams, int T,
     int tiles_per_wg) {
+  typedef typename VecT<VB>::type V;
+  constexpr int MAXV = 64 / VB;                  // register vectors per thread
+  constexpr int EPV = VB / (int)sizeof(IT);      // samples per vector
+  constexpr int WPV = VB / 4;                    // 32-bit words per vector
   extern __shared__ _Float16 sm[];
   const int RKP = KS * 16 + 8;
   const int s = blockIdx.y;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
   const int wn = wave % WN, wm = wave / WN, WM = 4 / WN;
   const int kq = lane >> 4, col16 = lane & 15;
+  const int nvec = T * RK / EPV;
 
-  half4 wreg[NPW][kBfKsMax];
+  half4 wreg[NPW][KSM];
 #pragma unroll
   for (int p = 0; p < NPW; ++p) {
     int nt = wn + p * WN;
 #pragma unroll
-    for (int ks = 0; ks < kBfKsMax; ++ks) {
+    for (int ks = 0; ks < KSM; ++ks) {
       half4 z = {0, 0, 0, 0};
       wreg[p][ks] = (nt < NT && ks < KS)
                         ? wf[((long)(s * NT + nt) * KS + ks) * 64 + lane]
                         : z;
     }
   }
+  // Columns RK .. KS*16-1 multiply zero weights but must not hold NaN
+  // patterns: zero them once (the tiles never write them).
+  const int padc = KS * 16 - RK;
+  for (int i = tid; i < T * padc; i += kBfThreads)
+    sm[(i / padc) * RKP + RK + (i % padc)] = (_Float16)0.0f;
 
-  const int mt_per_wave = (kBfT / 16) / WM;
+  V pre[MAXV];
+  auto fetch = [&](long t0) {
+    const V *src = reinterpret_cast<const V *>(x + ((long)s * n_t + t0) * RK);
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      int v = tid + kBfThreads * i;
+      if (v < nvec) pre[i] = __builtin_nontemporal_load(src + v);
+    }
+  };
+  auto deposit = [&]() {
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      int v = tid + kBfThreads * i;
+      if (v < nvec) {
+        int e0 = v * EPV, row = e0 / RK, col = e0 - row * RK;
+        unsigned w[WPV];
+        __builtin_memcpy(w, &pre[i], VB);
+        half2v h[EPV / 2];
+        int o = 0;
+#pragma unroll
+        for (int q = 0; q < WPV; ++q) o += word_to_half2<IT>(w[q], h + o);
+        if (scaled) {
+#pragma unroll
+          for (int q = 0; q < EPV / 2; ++q) {
+            half2v sc = {xscale[col + 2 * q], xscale[col + 2 * q + 1]};
+            h[q] = h[q] * sc;
+          }
+        }
+        _Float16 *dst = sm + row * RKP + col;
+        if constexpr (EPV % 8 == 0) {
+#pragma unroll
+          for (int q = 0; q < EPV / 8; ++q) {
+            int4 c;
+            __builtin_memcpy(&c, h + 4 * q, 16);
+            *reinterpret_cast<int4 *>(dst + 8 * q) = c;
+          }
+        } else if constexpr (EPV == 4) {
+          int2 c;
+          __builtin_memcpy(&c, h, 8);
+          *reinterpret_cast<int2 *>(dst) = c;
+        } else {
+          int c;
+          __builtin_memcpy(&c, h, 4);
+          *reinterpret_cast<int *>(dst) = c;
+        }
+      }
+    }
+  };
+
+  const long tile0 = (long)blockIdx.x * tiles_per_wg;
+  if (tile0 * T >= n_t) return;
+  fetch(tile0 * T);
+  const int mt_per_wave = (T / 16) / WM;
   for (int tile = 0; tile < tiles_per_wg; ++tile) {
-    long t0 = ((long)blockIdx.x * tiles_per_wg + tile) * kBfT;
+    const long t0 = (tile0 + tile) * T;
     if (t0 >= n_t) break;
+    __syncthreads();  // the previous tile's LDS reads are done
+    deposit();
     __syncthreads();
-    stage_tile_f16<IT, VB>(x + ((long)s * n_t + t0) * RK, RK, RKP, KS, xscale,
-                           scaled != 0, sm);
-    __syncthreads();
+    if (tile + 1 < tiles_per_wg && t0 + T < n_t) fetch(t0 + T);
     for (int mi = 0; mi < mt_per_wave; ++mi) {
       int mt = wm * mt_per_wave + mi;
       int row = mt * 16 + col16;
@@ -196,7 +251,7 @@ __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
 #pragma unroll
       for (int p = 0; p < NPW; ++p) acc[p] = floatx4{0, 0, 0, 0};
 #pragma unroll
-      for (int ks = 0; ks < kBfKsMax; ++ks) {
+      for (int ks = 0; ks < KSM; ++ks) {
         if (ks < KS) {
           half4 a = *reinterpret_cast<const half4 *>(sm + row * RKP + ks * 16 +
                                                      4 * kq);
@@ -395,10 +450,17 @@ static lp_status launch_bf(const BfPlan *p, const void *x, long n_t, int n_sb,
     const int NT = p->NT, KS = p->KS;
     const int WN = (NT == 1) ? 1 : (NT == 2) ? 2 : 4;
     const int npw = (NT + WN - 1) / WN;
-    const int tiles = (int)(n_t / kBfT);
-    const int tpw = tiles >= 4 ? 4 : 1;
-    dim3 grid((tiles + tpw - 1) / tpw, n_sb);
-    size_t shm = (size_t)kBfT * (KS * 16 + 8) * 2;
+    // Rows per tile: at most 64 bytes of input per thread (the prefetch
+    // registers), a multiple of 64 rows so the m-tiles split over waves.
+    int T = 128;
+    while (T > 64 && (long)T * row_bytes > 64L * kBfThreads) T -= 64;
+    if ((long)T * row_bytes > 64L * kBfThreads)
+      return set_error(LP_EINVAL, "beamformer: %d-byte time rows too long",
+                       row_bytes);
+    const long tiles = n_t / T;
+    const int tpw = tiles >= 64 ? 8 : tiles >= 8 ? 4 : 1;
+    dim3 grid((unsigned)((tiles + tpw - 1) / tpw), n_sb);
+    size_t shm = (size_t)T * (KS * 16 + 8) * 2;
     auto args = [&](auto kern) {
       LP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -407,18 +469,18 @@ static lp_status launch_bf(const BfPlan *p, const void *x, long n_t, int n_sb,
                          static_cast<const IT *>(x), p->w.as<const half4>(),
                          p->xscale.as<const _Float16>(), (int)p->scaled,
                          static_cast<float2 *>(y), n_sb, n_t, RK, KS, NT, WN,
-                         p->n_beams, tpw);
+                         p->n_beams, T, tpw);
       return LP_OK;
     };
+    const bool small_k = KS <= 8;
     lp_status rc;
-    if (npw == 1)
-      rc = (vb == 16)  ? args(bf_mfma_kernel<IT, 16, 1>)
-           : (vb == 8) ? args(bf_mfma_kernel<IT, 8, 1>)
-                       : args(bf_mfma_kernel<IT, 4, 1>);
-    else
-      rc = (vb == 16)  ? args(bf_mfma_kernel<IT, 16, 2>)
-           : (vb == 8) ? args(bf_mfma_kernel<IT, 8, 2>)
-                       : args(bf_mfma_kernel<IT, 4, 2>);
+#define LP_BF_PICK(VB_)                                                   \
+    (npw == 1 ? (small_k ? args(bf_mfma_kernel<IT, VB_, 1, 8>)            \
+                         : args(bf_mfma_kernel<IT, VB_, 1, 16>))          \
+              : (small_k ? args(bf_mfma_kernel<IT, VB_, 2, 8>)            \
+                         : args(bf_mfma_kernel<IT, VB_, 2, 16>)))
+    rc = (vb == 16) ? LP_BF_PICK(16) : (vb == 8) ? LP_BF_PICK(8) : LP_BF_PICK(4);
+#undef LP_BF_PICK
     if (rc) return rc;
   } else {
     int G = p->n_beams >= 4 ? 4 : p->n_beams >= 2 ? 2 : 1;

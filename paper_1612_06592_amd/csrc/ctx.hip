@@ -239,7 +239,7 @@ size_t lp_trigger_work_bytes(int32_t n_beams, int32_t n_tec) {
   return ns * 16                                   // count, sigma, peak, pad
          + ns * kTrigPerSeries * 16                // per-series lists
          + (size_t)n_beams * 16                    // per-beam counts
-         + (size_t)n_beams * 2 * n_tec * kTrigPerSeries * sizeof(lp_trig);
+         + (size_t)n_beams * n_tec * kTrigPerSeries * sizeof(lp_trig);
 }
 
 }  // extern "C"

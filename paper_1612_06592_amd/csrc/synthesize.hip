@@ -56,26 +56,34 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
   for (int t = 0; t < 16; ++t) win[t] = make_float2(0.f, 0.f);
 
   const int n_chunk = F / 16;
+  // Pass-0 inputs of a chunk: bins j + 64 r (r < 8; bins >= 512 are empty)
+  // of frame mc + f, from d or, before the block, from the history.
+  float2 pre[8];
+  auto fetch = [&](long mc_) {
+    const int jo = opaque(j), fo = opaque(f);
+    const long m = mc_ + fo;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      int si = binmap[jo + 64 * r];
+      pre[r] = make_float2(0.f, 0.f);
+      if (si >= 0)
+        pre[r] = (m >= 0) ? ds[(long)si * n_t + m]
+                          : hs[si * kSynHist + (kSynHist + m)];
+    }
+  };
+  fetch(m0 - 16);
   for (int c = -1; c < n_chunk; ++c) {
     const long mc = m0 + 16L * c;  // first frame of the chunk
     // Per-chunk opaque copies of the thread indices keep address arithmetic
     // inside the loop (hoisted, it would not fit in registers).
     const int jo = opaque(j), no = opaque(n), fo = opaque(f);
     const int lo = opaque(lane), wo = opaque(wave);
-    // ---- pass 0 (radix 16, Ns = 1): bins j + 64 r; bins >= 512 are empty.
+    // ---- pass 0 (radix 16, Ns = 1).
     float2 v[16];
-    {
-      const long m = mc + fo;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
+    for (int r = 0; r < 8; ++r) v[r] = pre[r];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        int si = binmap[jo + 64 * r];
-        if (si >= 0)
-          v[r] = (m >= 0) ? ds[(long)si * n_t + m]
-                          : hs[si * kSynHist + (kSynHist + m)];
-      }
-    }
+    for (int r = 8; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
     dft16<true>(v);
     __syncthreads();  // previous chunk's FIR reads of lds are done
     {
@@ -126,6 +134,8 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
       }
     }
     __syncthreads();
+    // Next chunk's inputs are in flight while this chunk is filtered.
+    if (c + 1 < n_chunk) fetch(mc + 16);
     // ---- FIR, envelope, statistics for the 16 frames of this chunk.
     if (c < 0) {
 #pragma unroll

@@ -8,8 +8,8 @@
 //   trials are chained while consecutive samples are at most M apart, each
 //   chain keeping its highest SNR (lowest trial, then earliest on ties).
 //
-// Three small kernels: per series (sigma, runs), per beam (merge), and one
-// ordered compaction into the caller's list.  All reductions have a fixed
+// Two small kernels: per series (sigma, runs) and one merge over beams in
+// beam order into the caller's list.  All reductions have a fixed
 // order, so the result is bitwise reproducible.
 #include <cmath>
 
@@ -34,7 +34,7 @@ struct WorkLayout {
   float *ser_peak;     // [ns]
   SerTrig *ser_list;   // [ns][kTrigPerSeries]
   int *beam_cnt;       // [nb]
-  lp_trig *beam_list;  // [nb][2][n_tec * kTrigPerSeries]: out | sorted
+  lp_trig *beam_list;  // [nb][n_tec * kTrigPerSeries] rank-sorted
 };
 
 static WorkLayout layout(void *work, int n_beams, int n_tec) {
@@ -57,12 +57,18 @@ static WorkLayout layout(void *work, int n_beams, int n_tec) {
 }
 
 constexpr int kT1Threads = 1024;
+constexpr long kMaxTrigWindows = 1L << 20;  // fired-window bitmask in LDS
 
-// One workgroup per series.
+// One workgroup per series.  Pass A: coalesced reads of the window maxima;
+// each wave's ballot gives the fired bits of 64 consecutive windows (LDS
+// bitmask).  Pass B: each thread scans a contiguous range of the bitmask
+// for run starts (a fired window whose predecessor did not fire); a
+// fixed-order scan of the counts gives each run its slot.
 __global__ __launch_bounds__(kT1Threads) void trig_series_kernel(
     const SynCand *__restrict__ cand, const float *__restrict__ psum,
     long n_t, long frame0, long warm, float k_sigma, long offset,
     WorkLayout w) {
+  extern __shared__ unsigned bits[];          // n_t / 32 words
   __shared__ double sred[kT1Threads / 64];
   __shared__ float fred[kT1Threads / 64];
   __shared__ int ired[kT1Threads / 64];
@@ -86,47 +92,72 @@ __global__ __launch_bounds__(kT1Threads) void trig_series_kernel(
   const float sigma =
       n_valid_fr > 0 ? (float)sqrt(tot / ((double)n_valid_fr * kM)) : 0.0f;
   const float thr = k_sigma * sigma;
+  const float inv_sigma = sigma > 0.0f ? 1.0f / sigma : 0.0f;
 
-  // Each thread owns a contiguous range of windows.
-  const long per = (n_t + kT1Threads - 1) / kT1Threads;
-  const long w0 = (long)tid * per, w1 = min(n_t, w0 + per);
-  auto fired = [&](long m) {
-    return m >= first_valid && sigma > 0.0f && cq[m].emax > thr;
-  };
+  // Pass A.
   float pk = 0.0f;
-  int n_runs = 0;
-  for (long m = w0; m < w1; ++m) {
-    if (m >= first_valid && sigma > 0.0f) pk = fmaxf(pk, cq[m].emax / sigma);
-    if (fired(m) && !(m > 0 && fired(m - 1))) ++n_runs;
+  for (long base = (long)wave * 64; base < n_t; base += kT1Threads) {
+    long m = base + lane;
+    bool valid = m < n_t && m >= first_valid && sigma > 0.0f;
+    float e = m < n_t ? cq[m].emax : 0.0f;
+    if (valid) pk = fmaxf(pk, e / sigma);
+    unsigned long long b = __ballot(valid && e > thr);
+    if (lane == 0) {
+      bits[base / 32] = (unsigned)b;
+      if (base / 32 + 1 < (n_t + 31) / 32) bits[base / 32 + 1] = (unsigned)(b >> 32);
+    }
   }
-  // Peak SNR: max over threads (order-free).
   for (int off = 32; off >= 1; off >>= 1) pk = fmaxf(pk, __shfl_xor(pk, off));
-  // Exclusive scan of run counts (deterministic positions).
+  if (lane == 0) fred[wave] = pk;
+  __syncthreads();
+
+  // Pass B.
+  const long nw = (n_t + 31) / 32;
+  const long per = (nw + kT1Threads - 1) / kT1Threads;
+  const long w0 = (long)tid * per, w1 = min(nw, w0 + per);
+  auto starts_of = [&](long wi) {
+    unsigned b = bits[wi];
+    unsigned prev = wi > 0 ? bits[wi - 1] >> 31 : 0u;
+    return b & ~((b << 1) | prev);
+  };
+  int n_runs = 0;
+  for (long wi = w0; wi < w1; ++wi) n_runs += __popc(starts_of(wi));
   int incl = n_runs;
   for (int off = 1; off < 64; off <<= 1) {
     int o = __shfl_up(incl, off);
     if (lane >= off) incl += o;
   }
   if (lane == 63) ired[wave] = incl;
-  if (lane == 0) fred[wave] = pk;
   __syncthreads();
   int wave_off = 0;
   for (int i = 0; i < wave; ++i) wave_off += ired[i];
   int pos = wave_off + incl - n_runs;
   if (tid == kT1Threads - 1) s_total = wave_off + incl;
-  for (long m = w0; m < w1; ++m) {
-    if (!(fired(m) && !(m > 0 && fired(m - 1)))) continue;
-    long best = m;
-    for (long e = m + 1; e < n_t && fired(e); ++e)
-      if (cq[e].emax > cq[best].emax) best = e;
-    if (pos < kTrigPerSeries) {
-      SerTrig t;
-      t.sample = (frame0 + best) * kM + cq[best].arg - offset;
-      t.peak = cq[best].emax;
-      t.snr = cq[best].emax / sigma;
-      w.ser_list[(long)q * kTrigPerSeries + pos] = t;
+  auto fired = [&](long m) { return (bits[m >> 5] >> (m & 31)) & 1u; };
+  for (long wi = w0; wi < w1; ++wi) {
+    unsigned st = starts_of(wi);
+    while (st) {
+      int bit = __ffs(st) - 1;
+      st &= st - 1;
+      long m = wi * 32 + bit;
+      long best = m;
+      float bv = cq[m].emax;
+      for (long e = m + 1; e < n_t && fired(e); ++e) {
+        float ev = cq[e].emax;
+        if (ev > bv) {
+          bv = ev;
+          best = e;
+        }
+      }
+      if (pos < kTrigPerSeries) {
+        SerTrig t;
+        t.sample = (frame0 + best) * kM + cq[best].arg - offset;
+        t.peak = bv;
+        t.snr = bv * inv_sigma;
+        w.ser_list[(long)q * kTrigPerSeries + pos] = t;
+      }
+      ++pos;
     }
-    ++pos;
   }
   __syncthreads();
   if (tid == 0) {
@@ -140,107 +171,90 @@ __global__ __launch_bounds__(kT1Threads) void trig_series_kernel(
 
 constexpr int kT2Threads = 256;
 
-// One workgroup per beam: rank-sort the trials' triggers by (sample,
-// trial), then chain and keep each chain's best.
-__global__ __launch_bounds__(kT2Threads) void trig_beam_kernel(
-    int n_tec, WorkLayout w, float *__restrict__ snr_out,
-    int *__restrict__ best_tec, float *__restrict__ sigma_out) {
-  const int b = blockIdx.x, tid = threadIdx.x;
-  const int cap = n_tec * kTrigPerSeries;
-  lp_trig *bl = w.beam_list + (long)b * 2 * cap;  // chain representatives
-  lp_trig *srt = bl + cap;                        // rank-sorted triggers
-  __shared__ int s_off[65];
-  if (tid == 0) {
-    int o = 0;
-    for (int j = 0; j < n_tec; ++j) {
-      int c = min(w.ser_cnt[b * n_tec + j], kTrigPerSeries);
-      o += c;
-    }
-    s_off[0] = o;
-  }
-  __syncthreads();
-  const int N = s_off[0];
-  // Ranks are unique, so each trigger lands in its own sorted slot.
-  for (int i = tid; i < N; i += kT2Threads) {
-    // Locate element i: walk trials.
-    int j = 0, r = i;
-    while (r >= min(w.ser_cnt[b * n_tec + j], kTrigPerSeries)) {
-      r -= min(w.ser_cnt[b * n_tec + j], kTrigPerSeries);
-      ++j;
-    }
-    SerTrig ti = w.ser_list[(long)(b * n_tec + j) * kTrigPerSeries + r];
-    int rank = 0;
-    for (int jj = 0; jj < n_tec; ++jj) {
-      int c = min(w.ser_cnt[b * n_tec + jj], kTrigPerSeries);
-      const SerTrig *L = w.ser_list + (long)(b * n_tec + jj) * kTrigPerSeries;
-      for (int rr = 0; rr < c; ++rr) {
-        long long sj = L[rr].sample;
-        if (sj < ti.sample || (sj == ti.sample && jj < j)) ++rank;
-      }
-    }
-    lp_trig o;
-    o.sample = ti.sample;
-    o.beam = b;
-    o.tec = j;
-    o.snr = ti.snr;
-    o.peak = ti.peak;
-    srt[rank] = o;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    // Walk the sorted list and keep one representative per chain.
-    int out = 0;
-    int i = 0;
-    while (i < N) {
-      lp_trig best = srt[i];
-      long long prev = best.sample;
-      int e = i + 1;
-      while (e < N) {
-        lp_trig c = srt[e];
-        if (c.sample - prev > kM) break;
-        if (c.snr > best.snr ||
-            (c.snr == best.snr &&
-             (c.tec < best.tec || (c.tec == best.tec && c.sample < best.sample))))
-          best = c;
-        prev = c.sample;
-        ++e;
-      }
-      bl[out++] = best;
-      i = e;
-    }
-    w.beam_cnt[b] = out;
-    int bj = 0;
-    float bp = w.ser_peak[b * n_tec];
-    for (int j = 0; j < n_tec; ++j) {
-      float pj = w.ser_peak[b * n_tec + j];
-      if (snr_out) snr_out[b * n_tec + j] = pj;
-      if (sigma_out) sigma_out[b * n_tec + j] = w.ser_sigma[b * n_tec + j];
-      if (pj > bp) {
-        bp = pj;
-        bj = j;
-      }
-    }
-    if (best_tec) best_tec[b] = bj;
-  }
-}
-
-// Ordered compaction of the per-beam lists into the caller's array.
-__global__ __launch_bounds__(256) void trig_compact_kernel(
+// One workgroup for all beams, in beam order: rank-sort each beam's
+// triggers of all trials by (sample, trial), chain them, and append each
+// chain's best to the caller's list (which is therefore ordered by beam,
+// then sample).
+__global__ __launch_bounds__(kT2Threads) void trig_merge_kernel(
     int n_beams, int n_tec, WorkLayout w, lp_trig *__restrict__ out, int cap,
-    int *__restrict__ n_out) {
-  __shared__ int s_base;
-  const int stride = 2 * n_tec * kTrigPerSeries;
-  int base = 0;
+    int *__restrict__ n_out, float *__restrict__ snr_out,
+    int *__restrict__ best_tec, float *__restrict__ sigma_out) {
+  const int tid = threadIdx.x;
+  const int bcap = n_tec * kTrigPerSeries;
+  __shared__ int s_n;
+  int base = 0;  // meaningful in thread 0
   for (int b = 0; b < n_beams; ++b) {
-    int c = w.beam_cnt[b];
-    for (int i = threadIdx.x; i < c; i += blockDim.x)
-      if (base + i < cap) out[base + i] = w.beam_list[(long)b * stride + i];
-    base += c;
+    lp_trig *srt = w.beam_list + (long)b * bcap;
+    if (tid == 0) {
+      int o = 0;
+      for (int j = 0; j < n_tec; ++j)
+        o += min(w.ser_cnt[b * n_tec + j], kTrigPerSeries);
+      s_n = o;
+    }
+    __syncthreads();
+    const int N = s_n;
+    for (int i = tid; i < N; i += kT2Threads) {
+      int j = 0, r = i;
+      while (r >= min(w.ser_cnt[b * n_tec + j], kTrigPerSeries)) {
+        r -= min(w.ser_cnt[b * n_tec + j], kTrigPerSeries);
+        ++j;
+      }
+      SerTrig ti = w.ser_list[(long)(b * n_tec + j) * kTrigPerSeries + r];
+      int rank = 0;
+      for (int jj = 0; jj < n_tec; ++jj) {
+        int c = min(w.ser_cnt[b * n_tec + jj], kTrigPerSeries);
+        const SerTrig *L = w.ser_list + (long)(b * n_tec + jj) * kTrigPerSeries;
+        for (int rr = 0; rr < c; ++rr) {
+          long long sj = L[rr].sample;
+          if (sj < ti.sample || (sj == ti.sample && jj < j)) ++rank;
+        }
+      }
+      lp_trig o;
+      o.sample = ti.sample;
+      o.beam = b;
+      o.tec = j;
+      o.snr = ti.snr;
+      o.peak = ti.peak;
+      srt[rank] = o;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int i = 0;
+      while (i < N) {
+        lp_trig best = srt[i];
+        long long prev = best.sample;
+        int e = i + 1;
+        while (e < N) {
+          lp_trig c = srt[e];
+          if (c.sample - prev > kM) break;
+          if (c.snr > best.snr ||
+              (c.snr == best.snr &&
+               (c.tec < best.tec ||
+                (c.tec == best.tec && c.sample < best.sample))))
+            best = c;
+          prev = c.sample;
+          ++e;
+        }
+        if (base < cap) out[base] = best;
+        ++base;
+        i = e;
+      }
+      int bj = 0;
+      float bp = w.ser_peak[b * n_tec];
+      for (int j = 0; j < n_tec; ++j) {
+        float pj = w.ser_peak[b * n_tec + j];
+        if (snr_out) snr_out[b * n_tec + j] = pj;
+        if (sigma_out) sigma_out[b * n_tec + j] = w.ser_sigma[b * n_tec + j];
+        if (pj > bp) {
+          bp = pj;
+          bj = j;
+        }
+      }
+      if (best_tec) best_tec[b] = bj;
+    }
+    __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    s_base = base;
-    *n_out = s_base;
-  }
+  if (tid == 0) *n_out = base;
 }
 
 }  // namespace lp
@@ -257,7 +271,7 @@ extern "C" lp_status lp_trigger(lp_ctx *ctx, const void *cand, int32_t n_beams,
     return set_error(LP_EINVAL, "lp_trigger: NULL argument");
   if (n_beams <= 0 || n_tec <= 0 || (long)n_beams * n_tec > 65535)
     return set_error(LP_EINVAL, "lp_trigger: bad n_beams/n_tec");
-  if (n_t <= 0 || n_t % kHop != 0)
+  if (n_t <= 0 || n_t % kHop != 0 || n_t > kMaxTrigWindows)
     return set_error(LP_EINVAL, "lp_trigger: n_t %lld", (long long)n_t);
   if (frame0 < 0 || !(k_sigma > 0.0f) || cap < 0)
     return set_error(LP_EINVAL, "lp_trigger: bad frame0/k_sigma/cap");
@@ -272,15 +286,17 @@ extern "C" lp_status lp_trigger(lp_ctx *ctx, const void *cand, int32_t n_beams,
   const SynCand *cd = reinterpret_cast<const SynCand *>(cb);
   const float *ps = reinterpret_cast<const float *>(cb + (size_t)ns * n_t * 8);
   const long offset = (long)kM * kTaps + (long)kDelay * kM;
-  hipLaunchKernelGGL(trig_series_kernel, dim3(ns), dim3(kT1Threads), 0, st,
+  const size_t shm = (size_t)((n_t + 31) / 32) * 4;
+  LP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(trig_series_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)shm));
+  hipLaunchKernelGGL(trig_series_kernel, dim3(ns), dim3(kT1Threads), shm, st,
                      cd, ps, (long)n_t, (long)frame0, (long)(kDelay + kTaps),
                      k_sigma, offset, w);
   LP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(trig_beam_kernel, dim3(n_beams), dim3(kT2Threads), 0, st,
-                     n_tec, w, snr_out, best_tec, sigma_out);
-  LP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(trig_compact_kernel, dim3(1), dim3(256), 0, st, n_beams,
-                     n_tec, w, out, cap, n_out);
+  hipLaunchKernelGGL(trig_merge_kernel, dim3(1), dim3(kT2Threads), 0, st,
+                     n_beams, n_tec, w, out, cap, n_out, snr_out, best_tec,
+                     sigma_out);
   LP_HIP(hipGetLastError());
   return LP_OK;
 }
