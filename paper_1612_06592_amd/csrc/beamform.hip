@@ -151,8 +151,8 @@ template <typename IT, int VB, int NPW, int KSM>
 __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
     const IT *__restrict__ x, const half4 *__restrict__ wf,
     const _Float16 *__restrict__ xscale, int scaled, float2 *__restrict__ y,
-    int n_sb, long n_t, int RK, int KS, int NT, int WN, int n_beams, int T,
-    int tiles_per_wg) {
+    int n_sb, long n_t, long x_nt, int RK, int KS, int NT, int WN,
+    int n_beams, int T, int tiles_per_wg) {
   typedef typename VecT<VB>::type V;
   constexpr int MAXV = 64 / VB;                  // register vectors per thread
   constexpr int EPV = VB / (int)sizeof(IT);      // samples per vector
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
 
   V pre[MAXV];
   auto fetch = [&](long t0) {
-    const V *src = reinterpret_cast<const V *>(x + ((long)s * n_t + t0) * RK);
+    const V *src = reinterpret_cast<const V *>(x + ((long)s * x_nt + t0) * RK);
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       int v = tid + kBfThreads * i;
@@ -292,8 +292,8 @@ __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
 template <typename IT, int VB>
 __global__ __launch_bounds__(kBfThreads) void bf_fp32_kernel(
     const IT *__restrict__ x, const float2 *__restrict__ w,
-    float2 *__restrict__ y, int n_sb, long n_t, int n_in, int n_beams,
-    int G) {
+    float2 *__restrict__ y, int n_sb, long n_t, long x_nt, int n_in,
+    int n_beams, int G) {
   extern __shared__ float smf[];
   const int T = kBfThreads / G;
   const int RK = 2 * n_in, RKP = RK + 1;
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(kBfThreads) void bf_fp32_kernel(
   const int rows = (int)min((long)T, n_t - t0);
   constexpr int EPV = VB / (int)sizeof(IT);
   const char *base =
-      reinterpret_cast<const char *>(x + ((long)s * n_t + t0) * RK);
+      reinterpret_cast<const char *>(x + ((long)s * x_nt + t0) * RK);
   const int nvec = rows * RK / EPV;
   for (int v = threadIdx.x; v < nvec; v += kBfThreads) {
     int e0 = v * EPV, row = e0 / RK, col = e0 - row * RK;
@@ -441,8 +441,8 @@ lp_status get_bf_plan(lp_ctx *ctx, const lp_array *a, const lp_band *band,
 }
 
 template <typename IT>
-static lp_status launch_bf(const BfPlan *p, const void *x, long n_t, int n_sb,
-                           void *y, hipStream_t st) {
+static lp_status launch_bf(const BfPlan *p, const void *x, long x_nt,
+                           long n_t, int n_sb, void *y, hipStream_t st) {
   const int n_in = p->n_in, RK = 2 * n_in;
   const int row_bytes = RK * (int)sizeof(IT);
   const int vb = (row_bytes % 16 == 0) ? 16 : (row_bytes % 8 == 0) ? 8 : 4;
@@ -468,8 +468,8 @@ static lp_status launch_bf(const BfPlan *p, const void *x, long n_t, int n_sb,
       hipLaunchKernelGGL(kern, grid, dim3(kBfThreads), shm, st,
                          static_cast<const IT *>(x), p->w.as<const half4>(),
                          p->xscale.as<const _Float16>(), (int)p->scaled,
-                         static_cast<float2 *>(y), n_sb, n_t, RK, KS, NT, WN,
-                         p->n_beams, T, tpw);
+                         static_cast<float2 *>(y), n_sb, n_t, x_nt, RK, KS,
+                         NT, WN, p->n_beams, T, tpw);
       return LP_OK;
     };
     const bool small_k = KS <= 8;
@@ -503,7 +503,7 @@ static lp_status launch_bf(const BfPlan *p, const void *x, long n_t, int n_sb,
                                  (int)shm));
       hipLaunchKernelGGL(kern, grid, dim3(kBfThreads), shm, st,
                          static_cast<const IT *>(x), p->w.as<const float2>(),
-                         static_cast<float2 *>(y), n_sb, n_t, n_in,
+                         static_cast<float2 *>(y), n_sb, n_t, x_nt, n_in,
                          p->n_beams, G);
       return LP_OK;
     };
@@ -552,7 +552,19 @@ extern "C" lp_status lp_beamform(lp_ctx *ctx, const lp_array *array,
   if ((rc = set_device(ctx))) return rc;
   BfPlan *p = nullptr;
   if ((rc = get_bf_plan(ctx, array, band, beams, n_beams, prec, &p))) return rc;
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  if (dtype == LP_CI8) return launch_bf<int8_t>(p, x, n_t, band->n_sb, y, st);
-  return launch_bf<int16_t>(p, x, n_t, band->n_sb, y, st);
+  return bf_launch(p, x, dtype, n_t, 0, n_t, band->n_sb, y,
+                   static_cast<hipStream_t>(hip_stream));
 }
+
+namespace lp {
+lp_status bf_launch(const BfPlan *p, const void *x, int dtype, long x_nt,
+                    long x_t0, long n_t, int n_sb, void *y, hipStream_t st) {
+  if (dtype == LP_CI8)
+    return launch_bf<int8_t>(p, static_cast<const int8_t *>(x) +
+                                    x_t0 * 2 * p->n_in,
+                             x_nt, n_t, n_sb, y, st);
+  return launch_bf<int16_t>(p, static_cast<const int16_t *>(x) +
+                                   x_t0 * 2 * p->n_in,
+                            x_nt, n_t, n_sb, y, st);
+}
+}  // namespace lp

@@ -144,17 +144,26 @@ extern "C" lp_status lp_dedisperse(lp_ctx *ctx, const lp_band *band,
   if ((rc = set_device(ctx))) return rc;
   DdPlan *p = nullptr;
   if ((rc = get_dd_plan(ctx, band, tec_tecu, n_tec, &p))) return rc;
+  return dd_launch(ctx, p, band->n_sb, y, n_beams, n_t, tail,
+                   !(flags & LP_DD_KEEP_TAIL), d,
+                   static_cast<hipStream_t>(hip_stream));
+}
+
+namespace lp {
+lp_status dd_launch(lp_ctx *ctx, const DdPlan *p, int n_sb, const void *y,
+                    int n_beams, long n_t, void *tail, bool update_tail,
+                    void *d, hipStream_t st) {
   const int n_hop = (int)(n_t / kHop);
-  const long nb = (long)n_beams * band->n_sb * n_hop;
+  const long nb = (long)n_beams * n_sb * n_hop;
   if (nb > 0x7fffffffL)
     return set_error(LP_EINVAL, "lp_dedisperse: grid too large");
-  hipLaunchKernelGGL(dd_kernel, dim3((unsigned)nb), dim3(kDdThreads), 0,
-                     static_cast<hipStream_t>(hip_stream),
+  hipLaunchKernelGGL(dd_kernel, dim3((unsigned)nb), dim3(kDdThreads), 0, st,
                      static_cast<const float2 *>(y), static_cast<float2 *>(tail),
-                     (flags & LP_DD_KEEP_TAIL) ? 0 : 1, static_cast<float2 *>(d),
+                     update_tail ? 1 : 0, static_cast<float2 *>(d),
                      ctx->tw4096.as<const float2>(), p->base.as<const float>(),
-                     p->afac.as<const float>(), p->rfk.as<const float>(),
-                     band->n_sb, n_tec, (long)n_t, n_hop, nb);
+                     p->afac.as<const float>(), p->rfk.as<const float>(), n_sb,
+                     p->n_tec, n_t, n_hop, nb);
   LP_HIP(hipGetLastError());
   return LP_OK;
 }
+}  // namespace lp

@@ -95,6 +95,24 @@ lp_status get_syn_plan(lp_ctx *ctx, const lp_band *band, SynPlan **out);
 lp_status check_band(const lp_band *band);
 lp_status set_device(lp_ctx *ctx);
 
+// Stage launches on an explicit stream, without argument checks (the
+// public entry points and the serving loop validate first).
+//   x rows of subband s start at x + (s * x_nt + x_t0) * 2 * n_in samples;
+//   cand rows are cand_nt frames long and the block starts at cand_t0.
+lp_status bf_launch(const BfPlan *p, const void *x, int dtype, long x_nt,
+                    long x_t0, long n_t, int n_sb, void *y, hipStream_t st);
+lp_status dd_launch(lp_ctx *ctx, const DdPlan *p, int n_sb, const void *y,
+                    int n_beams, long n_t, void *tail, bool update_tail,
+                    void *d, hipStream_t st);
+lp_status syn_launch(lp_ctx *ctx, const SynPlan *p, int n_sb, const void *d,
+                     int n_series, long n_t, long frame0, void *hist,
+                     float *x_out, void *cand, long cand_nt, long cand_t0,
+                     hipStream_t st);
+lp_status trig_launch(const void *cand, int n_beams, int n_tec, long n_t,
+                      long frame0, float k_sigma, lp_trig *out, int cap,
+                      int *n_out, float *snr_out, int *best_tec,
+                      float *sigma_out, void *work, hipStream_t st);
+
 // Remap a linear block index so that consecutive logical blocks land on the
 // same XCD (blocks are dealt round-robin over the 8 XCDs of the chip).
 __device__ inline long xcd_remap(long bid, long nblocks) {

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     const short *__restrict__ binmap, const float *__restrict__ taps,
     const float2 *__restrict__ tw, float *__restrict__ x_out,
     SynCand *__restrict__ cand, float *__restrict__ psum, int n_sb, long n_t,
-    long frame0, long warm, int F) {
+    long frame0, long warm, int F, long cand_nt, long cand_t0) {
   __shared__ float2 lds[16 * kSynFs];
   __shared__ float red_s[16];
 
@@ -198,13 +198,13 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
         SynCand o;
         o.emax = sqrtf(bv);
         o.arg = bi;
-        cand[(long)series * n_t + mc + wo] = o;
+        cand[(long)series * cand_nt + cand_t0 + mc + wo] = o;
       }
     }
     if (tid == 64) {
       float sum = 0.f;
       for (int w = 0; w < 16; ++w) sum += red_s[w];
-      psum[(long)series * (n_t / 16) + mc / 16] = sum;
+      psum[(long)series * (cand_nt / 16) + (cand_t0 + mc) / 16] = sum;
     }
   }
 }
@@ -232,6 +232,15 @@ extern "C" lp_status lp_synthesize(lp_ctx *ctx, const lp_band *band,
   if ((rc = set_device(ctx))) return rc;
   SynPlan *p = nullptr;
   if ((rc = get_syn_plan(ctx, band, &p))) return rc;
+  return syn_launch(ctx, p, band->n_sb, d, n_series, n_t, frame0, hist, x_out,
+                    cand, n_t, 0, static_cast<hipStream_t>(hip_stream));
+}
+
+namespace lp {
+lp_status syn_launch(lp_ctx *ctx, const SynPlan *p, int n_sb, const void *d,
+                     int n_series, long n_t, long frame0, void *hist,
+                     float *x_out, void *cand, long cand_nt, long cand_t0,
+                     hipStream_t st) {
   // Frames per workgroup: long blocks amortise the 16-frame warm-up; short
   // ones keep enough workgroups to fill the chip.
   int F = 256;
@@ -239,13 +248,14 @@ extern "C" lp_status lp_synthesize(lp_ctx *ctx, const lp_band *band,
   const long n_wg = n_t / F;
   char *cb = static_cast<char *>(cand);
   SynCand *cd = reinterpret_cast<SynCand *>(cb);
-  float *ps = reinterpret_cast<float *>(cb + (size_t)n_series * n_t * 8);
+  float *ps = reinterpret_cast<float *>(cb + (size_t)n_series * cand_nt * 8);
   hipLaunchKernelGGL(syn_kernel, dim3((unsigned)n_wg, n_series),
-                     dim3(kSynThreads), 0, static_cast<hipStream_t>(hip_stream),
-                     static_cast<const float2 *>(d), static_cast<float2 *>(hist),
-                     p->binmap.as<const short>(), p->taps.as<const float>(),
-                     ctx->tw4096.as<const float2>(), x_out, cd, ps, band->n_sb,
-                     (long)n_t, (long)frame0, (long)(kDelay + kTaps), F);
+                     dim3(kSynThreads), 0, st, static_cast<const float2 *>(d),
+                     static_cast<float2 *>(hist), p->binmap.as<const short>(),
+                     p->taps.as<const float>(), ctx->tw4096.as<const float2>(),
+                     x_out, cd, ps, n_sb, n_t, frame0,
+                     (long)(kDelay + kTaps), F, cand_nt, cand_t0);
   LP_HIP(hipGetLastError());
   return LP_OK;
 }
+}  // namespace lp

@@ -279,7 +279,16 @@ extern "C" lp_status lp_trigger(lp_ctx *ctx, const void *cand, int32_t n_beams,
     return set_error(LP_EINVAL, "lp_trigger: work must be 16-byte aligned");
   lp_status rc;
   if ((rc = set_device(ctx))) return rc;
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  return trig_launch(cand, n_beams, n_tec, n_t, frame0, k_sigma, out, cap,
+                     n_out, snr_out, best_tec, sigma_out, work,
+                     static_cast<hipStream_t>(hip_stream));
+}
+
+namespace lp {
+lp_status trig_launch(const void *cand, int n_beams, int n_tec, long n_t,
+                      long frame0, float k_sigma, lp_trig *out, int cap,
+                      int *n_out, float *snr_out, int *best_tec,
+                      float *sigma_out, void *work, hipStream_t st) {
   const int ns = n_beams * n_tec;
   WorkLayout w = layout(work, n_beams, n_tec);
   const char *cb = static_cast<const char *>(cand);
@@ -291,8 +300,8 @@ extern "C" lp_status lp_trigger(lp_ctx *ctx, const void *cand, int32_t n_beams,
                              hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)shm));
   hipLaunchKernelGGL(trig_series_kernel, dim3(ns), dim3(kT1Threads), shm, st,
-                     cd, ps, (long)n_t, (long)frame0, (long)(kDelay + kTaps),
-                     k_sigma, offset, w);
+                     cd, ps, n_t, frame0, (long)(kDelay + kTaps), k_sigma,
+                     offset, w);
   LP_HIP(hipGetLastError());
   hipLaunchKernelGGL(trig_merge_kernel, dim3(1), dim3(kT2Threads), 0, st,
                      n_beams, n_tec, w, out, cap, n_out, snr_out, best_tec,
@@ -300,3 +309,4 @@ extern "C" lp_status lp_trigger(lp_ctx *ctx, const void *cand, int32_t n_beams,
   LP_HIP(hipGetLastError());
   return LP_OK;
 }
+}  // namespace lp
