@@ -209,6 +209,95 @@ lp_status lp_trigger(lp_ctx *ctx, const void *cand, int32_t n_beams,
                      float *snr_out, int32_t *best_tec, float *sigma_out,
                      void *work, void *hip_stream);
 
+/* ---- serving: concurrent observation streams ------------------------- */
+/* A persistent request loop (one host thread) runs the four stages for many
+ * observation streams.  Each open stream keeps its overlap-save tail and
+ * synthesis history resident in a caller-provided device arena; blocks are
+ * admitted as slots and arena space free up, split into hop-aligned chunks,
+ * and the next chunk is always taken from the admitted block with the
+ * earliest deadline.  Each stream has its own HIP stream, so the chunks of
+ * different streams overlap on the device.  Results are bitwise identical
+ * to running the same blocks through lp_beamform .. lp_trigger directly.
+ * The arena is carved by the server (first fit, 256-byte aligned); the
+ * caller keeps it allocated until lp_server_destroy returns. */
+
+typedef struct lp_server lp_server;
+
+typedef struct {
+  lp_array array;        /* copied at open                                 */
+  lp_band band;          /* copied at open                                 */
+  const lp_dir *beams;   /* [n_beams], copied at open                      */
+  int32_t n_beams;       /* 1..64                                          */
+  const double *tec_tecu;/* [n_tec], copied at open                        */
+  int32_t n_tec;
+  int32_t dtype;         /* LP_CI8 or LP_CI16                              */
+  int32_t prec;          /* LP_FP32 or LP_FP16_MFMA                        */
+  float k_sigma;         /* trigger threshold in sigma (6)                 */
+  int64_t max_n_t;       /* longest block this stream will submit          */
+  int32_t trig_cap;      /* triggers returned per block (0 = 1024)         */
+  double deadline_s;     /* per-block latency budget; 0 = the 5 s transient
+                            buffer minus the block's duration              */
+} lp_stream_cfg;
+
+typedef struct {
+  int32_t stream;          /* id from lp_stream_open                        */
+  int32_t status;          /* LP_OK, LP_ECLOSED (dropped at close), LP_EHIP */
+  uint64_t tag;            /* the submit's tag                              */
+  int64_t n_t;             /* block length (subband samples)                */
+  int64_t frame0;          /* stream index of the block's first sample      */
+  int32_t n_trig;          /* number of triggers (may exceed trig_cap)      */
+  int32_t n_beams, n_tec;
+  const lp_trig *trig;     /* host, min(n_trig, trig_cap) entries          */
+  const float *snr;        /* host [n_beams][n_tec] peak envelope / sigma  */
+  const int32_t *best_tec; /* host [n_beams]                                */
+  int64_t submit_ns;       /* host steady clock at submit                   */
+  int64_t done_ns;         /* host steady clock when the loop saw it done   */
+  int64_t latency_ns;      /* done_ns - submit_ns                           */
+  int64_t deadline_ns;     /* the block's latency budget                    */
+} lp_result;
+
+#define LP_SUBMIT_RESET 1  /* zero the stream state first (fresh stream)  */
+
+/* Bytes of arena a stream keeps while open (state + chunk buffers) and
+ * that one of its blocks of n_t samples holds while in flight.            */
+size_t lp_stream_resident_bytes(const lp_stream_cfg *cfg, int64_t chunk_t);
+size_t lp_block_bytes(const lp_stream_cfg *cfg, int64_t n_t);
+
+/* chunk_t: samples per subband processed per chunk (multiple of LP_HOP;
+ * 0 = 8192).  max_slots: blocks in flight at once (0 = 16). */
+lp_status lp_server_create(lp_ctx *ctx, void *arena_dev, size_t arena_bytes,
+                           int32_t max_slots, int64_t chunk_t,
+                           lp_server **out);
+/* A server whose executor only models time (ns_per_sample per station-beam
+ * sample on one in-order device queue) and computes nothing: the request
+ * loop, admission and scheduling run exactly as in the real server.  For
+ * tests without a GPU; results have no triggers. */
+lp_status lp_server_create_sim(double ns_per_sample, size_t arena_bytes,
+                               int32_t max_slots, int64_t chunk_t,
+                               lp_server **out);
+/* LP_EAGAIN if the stream's resident bytes do not fit in the arena now. */
+lp_status lp_stream_open(lp_server *srv, const lp_stream_cfg *cfg,
+                         int32_t *id);
+/* Queue a block: device memory [n_sb][n_t][n_st][n_pol] complex ints that
+ * stays valid and unchanged until its result is polled.  Returns at once;
+ * LP_EINVAL for a bad length (not a positive multiple of LP_HOP, or above
+ * max_n_t), LP_ECLOSED if the stream is closing. */
+lp_status lp_stream_submit(lp_server *srv, int32_t id, const void *block,
+                           int64_t n_t, uint64_t tag, int32_t flags);
+/* Wait up to timeout_us for results; returns up to cap of them in
+ * completion order.  The arrays they point to stay valid until the next
+ * lp_stream_poll on this server.  LP_ETIMEOUT if none arrived. */
+lp_status lp_stream_poll(lp_server *srv, lp_result *out, int32_t cap,
+                         int32_t *n, int32_t timeout_us);
+/* Blocks already admitted finish; blocks still queued are returned with
+ * status LP_ECLOSED; the stream's arena space is released afterwards. */
+lp_status lp_stream_close(lp_server *srv, int32_t id);
+/* Finishes admitted blocks, drops queued ones, stops the loop. */
+void lp_server_destroy(lp_server *srv);
+/* Aggregate counters: blocks done, chunks issued, admission waits. */
+lp_status lp_server_stats(lp_server *srv, int64_t *blocks_done,
+                          int64_t *chunks_issued, int64_t *admit_waits);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,6 +48,33 @@ class lp_dir(C.Structure):
     _fields_ = [("az_rad", C.c_double), ("el_rad", C.c_double)]
 
 
+class lp_trig(C.Structure):
+    _fields_ = [("sample", C.c_int64), ("beam", C.c_int32),
+                ("tec", C.c_int32), ("snr", C.c_float), ("peak", C.c_float)]
+
+
+class lp_stream_cfg(C.Structure):
+    _fields_ = [("array", lp_array), ("band", lp_band),
+                ("beams", C.POINTER(lp_dir)), ("n_beams", C.c_int32),
+                ("tec_tecu", C.POINTER(C.c_double)), ("n_tec", C.c_int32),
+                ("dtype", C.c_int32), ("prec", C.c_int32),
+                ("k_sigma", C.c_float), ("max_n_t", C.c_int64),
+                ("trig_cap", C.c_int32), ("deadline_s", C.c_double)]
+
+
+class lp_result(C.Structure):
+    _fields_ = [("stream", C.c_int32), ("status", C.c_int32),
+                ("tag", C.c_uint64), ("n_t", C.c_int64),
+                ("frame0", C.c_int64), ("n_trig", C.c_int32),
+                ("n_beams", C.c_int32), ("n_tec", C.c_int32),
+                ("trig", C.POINTER(lp_trig)), ("snr", C.POINTER(C.c_float)),
+                ("best_tec", C.POINTER(C.c_int32)),
+                ("submit_ns", C.c_int64), ("done_ns", C.c_int64),
+                ("latency_ns", C.c_int64), ("deadline_ns", C.c_int64)]
+
+
+LP_SUBMIT_RESET = 1
+
 TRIG_DTYPE = np.dtype([("sample", np.int64), ("beam", np.int32),
                        ("tec", np.int32), ("snr", np.float32),
                        ("peak", np.float32)])
@@ -92,6 +119,28 @@ def lib():
     for name in ("lp_beamform", "lp_dedisperse", "lp_synthesize",
                  "lp_trigger"):
         getattr(L, name).restype = i32
+    sp = C.POINTER(lp_stream_cfg)
+    L.lp_stream_resident_bytes.argtypes = [sp, i64]
+    L.lp_stream_resident_bytes.restype = C.c_size_t
+    L.lp_block_bytes.argtypes = [sp, i64]
+    L.lp_block_bytes.restype = C.c_size_t
+    L.lp_server_create.argtypes = [vp, vp, C.c_size_t, i32, i64,
+                                   C.POINTER(vp)]
+    L.lp_server_create_sim.argtypes = [C.c_double, C.c_size_t, i32, i64,
+                                       C.POINTER(vp)]
+    L.lp_stream_open.argtypes = [vp, sp, C.POINTER(i32)]
+    L.lp_stream_submit.argtypes = [vp, i32, vp, i64, C.c_uint64, i32]
+    L.lp_stream_poll.argtypes = [vp, C.POINTER(lp_result), i32,
+                                 C.POINTER(i32), i32]
+    L.lp_stream_close.argtypes = [vp, i32]
+    L.lp_server_destroy.argtypes = [vp]
+    L.lp_server_destroy.restype = None
+    L.lp_server_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64),
+                                  C.POINTER(i64)]
+    for name in ("lp_server_create", "lp_server_create_sim",
+                 "lp_stream_open", "lp_stream_submit", "lp_stream_poll",
+                 "lp_stream_close", "lp_server_stats"):
+        getattr(L, name).restype = i32
     _lib = L
     return L
 
@@ -101,7 +150,11 @@ def exported_symbols():
     return ["lp_last_error", "lp_version", "lp_ctx_create", "lp_ctx_destroy",
             "lp_beam_bytes", "lp_dd_state_bytes", "lp_dd_bytes",
             "lp_syn_state_bytes", "lp_cand_bytes", "lp_trigger_work_bytes",
-            "lp_beamform", "lp_dedisperse", "lp_synthesize", "lp_trigger"]
+            "lp_beamform", "lp_dedisperse", "lp_synthesize", "lp_trigger",
+            "lp_stream_resident_bytes", "lp_block_bytes", "lp_server_create",
+            "lp_server_create_sim", "lp_stream_open", "lp_stream_submit",
+            "lp_stream_poll", "lp_stream_close", "lp_server_destroy",
+            "lp_server_stats"]
 
 
 def check(rc: int):
@@ -327,3 +380,108 @@ class Pipeline:
         psum = c[ns * n_t * 8: ns * n_t * 8 + ns * (n_t // 16) * 4].view(
             torch.float32).view(ns, n_t // 16)
         return emax, arg, psum
+
+
+# ---------------------------------------------------------------- serving
+
+class StreamCfg:
+    """Keeps the host buffers of one lp_stream_cfg alive."""
+
+    def __init__(self, enu, k, az_el, tec, max_n_t: int, dtype: int = LP_CI8,
+                 prec: int = LP_FP16_MFMA, n_pol: int = 2, k_sigma: float = 6.0,
+                 trig_cap: int = 0, deadline_s: float = 0.0, gain=None):
+        self.array = Array(enu, n_pol, gain)
+        self.band = Band(k)
+        self.dirs = Dirs(az_el)
+        self.tec = np.ascontiguousarray(np.atleast_1d(tec), dtype=np.float64)
+        self.c = lp_stream_cfg(self.array.c, self.band.c, self.dirs.arr,
+                               self.dirs.n,
+                               self.tec.ctypes.data_as(C.POINTER(C.c_double)),
+                               len(self.tec), dtype, prec, k_sigma, max_n_t,
+                               trig_cap, deadline_s)
+
+    def resident_bytes(self, chunk_t: int = 0) -> int:
+        return int(lib().lp_stream_resident_bytes(C.byref(self.c), chunk_t))
+
+    def block_bytes(self, n_t: int) -> int:
+        return int(lib().lp_block_bytes(C.byref(self.c), n_t))
+
+
+class Server:
+    """lp_server_*: the persistent request loop (see include/lp.h)."""
+
+    def __init__(self, ctx: Ctx | None = None, arena=None, arena_bytes=None,
+                 max_slots: int = 0, chunk_t: int = 0,
+                 sim_ns_per_sample: float | None = None):
+        self.h = C.c_void_p()
+        self._cfgs = {}
+        self.arena = arena
+        if sim_ns_per_sample is not None:
+            check(lib().lp_server_create_sim(sim_ns_per_sample, arena_bytes,
+                                             max_slots, chunk_t,
+                                             C.byref(self.h)))
+        else:
+            check(lib().lp_server_create(ctx.h, _ptr(arena),
+                                         arena_bytes or arena.numel(),
+                                         max_slots, chunk_t, C.byref(self.h)))
+
+    def open(self, cfg: StreamCfg) -> int:
+        sid = C.c_int32()
+        check(lib().lp_stream_open(self.h, C.byref(cfg.c), C.byref(sid)))
+        self._cfgs[sid.value] = cfg
+        return sid.value
+
+    def submit(self, sid: int, block, n_t: int, tag: int = 0, flags: int = 0):
+        ptr = block if isinstance(block, (int, type(None))) else block.data_ptr()
+        check(lib().lp_stream_submit(self.h, sid, C.c_void_p(ptr), n_t, tag,
+                                     flags))
+
+    def poll(self, cap: int = 64, timeout_us: int = 100000):
+        """Returns a list of result dicts (copies)."""
+        arr = (lp_result * cap)()
+        n = C.c_int32()
+        rc = lib().lp_stream_poll(self.h, arr, cap, C.byref(n), timeout_us)
+        if rc == LP_ETIMEOUT:
+            return []
+        check(rc)
+        out = []
+        for r in arr[:n.value]:
+            nt = min(r.n_trig, self._cap(r.stream)) if r.status == LP_OK else 0
+            trig = np.zeros(nt, dtype=TRIG_DTYPE)
+            if nt:
+                C.memmove(trig.ctypes.data, r.trig, nt * TRIG_DTYPE.itemsize)
+            nbj = r.n_beams * r.n_tec
+            snr = np.ctypeslib.as_array(r.snr, (nbj,)).copy() if nbj else None
+            best = (np.ctypeslib.as_array(r.best_tec, (r.n_beams,)).copy()
+                    if r.n_beams else None)
+            out.append(dict(stream=r.stream, status=r.status, tag=r.tag,
+                            n_t=r.n_t, frame0=r.frame0, n_trig=r.n_trig,
+                            trig=trig, snr=snr, best_tec=best,
+                            submit_ns=r.submit_ns, done_ns=r.done_ns,
+                            latency_ns=r.latency_ns,
+                            deadline_ns=r.deadline_ns))
+        return out
+
+    def _cap(self, sid):
+        c = self._cfgs.get(sid)
+        return (c.c.trig_cap or 1024) if c is not None else 1024
+
+    def close_stream(self, sid: int):
+        check(lib().lp_stream_close(self.h, sid))
+
+    def stats(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        rc = lib().lp_server_stats(self.h, C.byref(a), C.byref(b), C.byref(c))
+        return dict(blocks_done=a.value, chunks_issued=b.value,
+                    admit_waits=c.value, status=rc)
+
+    def destroy(self):
+        if self.h:
+            lib().lp_server_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
