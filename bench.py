@@ -61,6 +61,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-hops", type=int, default=32,
                     help="hops (2048 samples each) in the oracle sample")
+    ap.add_argument("--duration", type=float, default=20.0,
+                    help="c5: seconds of Poisson arrivals")
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="c5: offered load as a fraction of the GPU")
+    ap.add_argument("--max-log2-nt", type=int, default=18,
+                    help="c5: longest block is 2^this samples per subband")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for "
                          "calibrating HBM byte counters)")
@@ -76,6 +82,8 @@ def main():
     import lofarsim
     from paper_1612_06592_amd import lp
 
+    if a.workload == "c5":
+        return serving_bench(a)
     cfg = lofarsim.get_config(a.workload)
     t0 = time.time()
     blk = lofarsim.generate(cfg)
@@ -209,6 +217,130 @@ def run_cpu_baseline(blk, hops: int):
                       f"(all {cfg.n_sb} subbands, {cfg.n_in} inputs, "
                       f"{cfg.n_beams} beams, {cfg.n_tec} trials)",
             "seconds": round(dt, 2)}
+
+
+def serving_bench(a):
+    """C5: concurrent observation streams through the serving loop."""
+    import threading
+
+    import torch
+
+    import lofarsim
+    from paper_1612_06592_amd import lp
+
+    dev = "cuda:0"
+    specs = lofarsim.serving_streams(12, max_log2_nt=a.max_log2_nt)
+    gen = torch.Generator(device=dev)
+    pools, cfgs = [], []
+    for sp in specs:
+        gen.manual_seed(sp["seed"])
+        rng = np.random.default_rng(sp["seed"])
+        n_in, n_sb = sp["n_st"] * 2, len(sp["k"])
+        nbytes = n_sb * (1 << a.max_log2_nt) * n_in * 2
+        pool = torch.empty(nbytes, dtype=torch.int8, device=dev)
+        step = 1 << 28
+        for o in range(0, nbytes, step):
+            m = min(step, nbytes - o)
+            v = torch.randn(m, generator=gen, device=dev) * 8.0
+            pool[o:o + m] = v.round_().clamp_(-127, 127).to(torch.int8)
+            del v
+        pools.append(pool)
+        enu = lofarsim.stations_in_disk(rng, sp["n_st"], 2000.0)
+        az0, el0 = lofarsim.moon_direction(rng)
+        rings = {7: 1, 19: 2, 37: 3, 61: 4}[sp["n_beams"]]
+        cfgs.append(lp.StreamCfg(enu, sp["k"], lofarsim.hex_beams(az0, el0, rings),
+                                 [sp["tec"]], 1 << a.max_log2_nt,
+                                 dtype=lp.LP_CI8, prec=lp.LP_FP16_MFMA,
+                                 trig_cap=256))
+    torch.cuda.synchronize()
+    print(f"[bench] c5: {len(specs)} stream pools generated", file=sys.stderr,
+          flush=True)
+    ctx = lp.Ctx(0)
+    chunk_t = 16384
+    arena_bytes = sum(c.resident_bytes(chunk_t) + c.block_bytes(1 << a.max_log2_nt)
+                      for c in cfgs) + (1 << 30)
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
+    srv = lp.Server(ctx, arena, arena_bytes, max_slots=16, chunk_t=chunk_t)
+    ids = [srv.open(c) for c in cfgs]
+    sbs = [c.array.n_in * c.band.n_sb * c.dirs.n for c in cfgs]
+
+    def run_alone(i, n_t):
+        srv.submit(ids[i], pools[i], n_t, tag=1 << 40)
+        while True:
+            r = srv.poll(timeout_us=1000000)
+            if r:
+                return r[0]
+
+    # Service time alone: one block of each length per stream (the first
+    # run also creates the stream's tables); a linear fit per stream.
+    lens = [1 << e for e in range(12, a.max_log2_nt + 1)]
+    svc = []
+    for i in range(len(ids)):
+        run_alone(i, lens[0])
+        t = [run_alone(i, n)["latency_ns"] * 1e-9 for n in lens]
+        svc.append(dict(zip(lens, t)))
+    mean_svc = [float(np.mean(list(d.values()))) for d in svc]
+    rate = [a.load / (len(ids) * m) for m in mean_svc]   # blocks per second
+    print(f"[bench] c5: calibrated; mean service ms "
+          f"{[round(m * 1e3, 2) for m in mean_svc]}", file=sys.stderr, flush=True)
+
+    # Poisson arrivals, block length log-uniform (uniform exponent).
+    rng = np.random.default_rng(7)
+    events = []
+    for i in range(len(ids)):
+        t = 0.0
+        while True:
+            t += rng.exponential(1.0 / rate[i])
+            if t > a.duration:
+                break
+            events.append((t, i, int(rng.choice(lens))))
+    events.sort()
+    results = []
+    done = threading.Event()
+
+    def poller():
+        while not (done.is_set() and len(results) >= len(events)):
+            results.extend(srv.poll(timeout_us=20000))
+
+    th = threading.Thread(target=poller)
+    th.start()
+    t_start = time.perf_counter()
+    for k, (t, i, n) in enumerate(events):
+        now = time.perf_counter() - t_start
+        if t > now:
+            time.sleep(t - now)
+        srv.submit(ids[i], pools[i], n, tag=k)
+    done.set()
+    th.join()
+    wall = time.perf_counter() - t_start
+    stats = srv.stats()
+    srv.destroy()
+    ctx.close()
+    ok = [r for r in results if r["status"] == lp.LP_OK]
+    lat = np.array([r["latency_ns"] for r in ok]) * 1e-6
+    dl = np.array([r["deadline_ns"] for r in ok]) * 1e-6
+    samples = sum(sbs[r["stream"] - ids[0]] * r["n_t"] for r in ok)
+    busy = sum(svc[r["stream"] - ids[0]][r["n_t"]] for r in ok)
+    out = {
+        "metric": METRIC, "value": round(samples / wall / 1e6, 1),
+        "unit": "Msamples/s", "n_gpus": 1, "steps": len(ok), "warmup": 0,
+        "ms_per_step": round(wall * 1e3 / max(1, len(ok)), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16-mfma/f32", "data": "synthetic",
+        "config": {"workload": "c5-serving", "streams": len(ids),
+                   "block_samples": [lens[0], lens[-1]], "chunk": chunk_t,
+                   "offered_load": a.load, "duration_s": a.duration},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3),
+                       "max": round(float(lat.max()), 3),
+                       "deadline_min": round(float(dl.min()), 1),
+                       "missed": int(np.sum(lat > dl))},
+        "blocks": {"done": len(ok), "failed": len(results) - len(ok),
+                   "chunks": stats["chunks_issued"],
+                   "admit_waits": stats["admit_waits"]},
+        "measured_load": round(busy / wall, 3),
+    }
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":

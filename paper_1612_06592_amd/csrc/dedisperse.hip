@@ -99,10 +99,12 @@ __attribute__((amdgpu_waves_per_eu(4, 8))) void dd_kernel(
       float x = (float)qs * rf;                     // nu_q / f_k
       // frac(kappa T/(f_k+nu)) = frac(A) - A x / (1 + x); the bulk delay
       // q_s D / 4096 = q_s / 4 contributes (q_s mod 4) / 4 exactly.
-      float c = bse - A * x / (1.0f + x) + 0.25f * (float)(qs & 3);
+      // The residual is below ~0.4 cycles, so a 1-ulp reciprocal adds < 1e-7
+      // cycles; the hardware sine/cosine take the phase in revolutions.
+      float c = bse - A * x * __builtin_amdgcn_rcpf(1.0f + x) +
+                0.25f * (float)(qs & 3);
       c -= rintf(c);
-      float sn, cs;
-      __sincosf(6.283185307179586f * c, &sn, &cs);
+      const float sn = __builtin_amdgcn_sinf(c), cs = __builtin_amdgcn_cosf(c);
       v[r] = cmul(U[r], make_float2(cs, -sn));
     }
     __syncthreads();  // previous trial's last LDS reads are done
