@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-hops", type=int, default=32,
                     help="hops (2048 samples each) in the oracle sample")
+    ap.add_argument("--plain-steps", type=int, default=3,
+                    help="steps of the plain FP32 comparator pipeline (0: skip)")
     ap.add_argument("--duration", type=float, default=20.0,
                     help="c5: seconds of Poisson arrivals")
     ap.add_argument("--load", type=float, default=0.8,
@@ -169,6 +171,29 @@ def main():
                                              * cfg.n_t * 1024)) <= 1
                     for t in trig) for pl in blk.pulses)
 
+    plain = None
+    if a.plain_steps > 0:
+        del p
+        torch.cuda.empty_cache()
+        pp = lp.Pipeline(ctx, lp.Array(blk.enu, 2), lp.Band(blk.k),
+                         lp.Dirs(blk.az_el), blk.tec, cfg.n_t,
+                         dtype=lp.LP_CI8 if cfg.dtype == "ci8" else lp.LP_CI16,
+                         prec=lp.LP_FP32, plain=True, device=dev)
+        pp.step(x)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for _ in range(a.plain_steps):
+            pp.step(x)
+        torch.cuda.synchronize()
+        ms_plain = (time.perf_counter() - tp) * 1e3 / a.plain_steps
+        plain = {"ms_per_step": round(ms_plain, 3),
+                 "value": round(samples / (ms_plain * 1e-3) / 1e6, 1),
+                 "speedup": round(ms_plain / ms_per_step, 2),
+                 "kind": "same stages, FP32 beamformer, every intermediate "
+                         "in HBM, radix-2 global-memory FFT passes"}
+        del pp
+        torch.cuda.empty_cache()
+
     cpu = None
     if not a.no_cpu_baseline:
         cpu = run_cpu_baseline(blk, a.cpu_hops)
@@ -193,6 +218,7 @@ def main():
         "stage_ms": {s: round(v, 4) for s, v in stage_avg.items()},
         "pulses_found": f"{found}/{len(blk.pulses)}",
         "roofline": roofline,
+        "plain_fp32_pipeline": plain,
         "cpu_baseline": cpu,
     }
     ctx.close()

@@ -209,6 +209,27 @@ lp_status lp_trigger(lp_ctx *ctx, const void *cand, int32_t n_beams,
                      float *snr_out, int32_t *best_tec, float *sigma_out,
                      void *work, void *hip_stream);
 
+/* ---- plain FP32 comparator ------------------------------------------- */
+/* The same de-dispersion and synthesis arithmetic organised the
+ * straightforward way: every intermediate (overlap-save buffers, spectra,
+ * each radix-2 FFT pass through global memory, filtered series, envelope,
+ * real series) is a full array in device memory and every step is its own
+ * kernel.  Arguments and outputs as lp_dedisperse / lp_synthesize (equal to
+ * FP32 rounding); `work` is device scratch of work_bytes, at least
+ * lp_plain_work_bytes (beams / series are processed in groups that fit).
+ * This is the baseline against which the fused kernels are measured. */
+size_t lp_plain_work_bytes(int32_t n_beams, int32_t n_tec, int32_t n_sb,
+                           int64_t n_t);
+lp_status lp_dedisperse_plain(lp_ctx *ctx, const lp_band *band,
+                              const double *tec_tecu, int32_t n_tec,
+                              const void *y, int32_t n_beams, int64_t n_t,
+                              void *tail, int32_t flags, void *d, void *work,
+                              size_t work_bytes, void *hip_stream);
+lp_status lp_synthesize_plain(lp_ctx *ctx, const lp_band *band, const void *d,
+                              int32_t n_series, int64_t n_t, int64_t frame0,
+                              void *hist, float *x_out, void *cand, void *work,
+                              size_t work_bytes, void *hip_stream);
+
 /* ---- serving: concurrent observation streams ------------------------- */
 /* A persistent request loop (one host thread) runs the four stages for many
  * observation streams.  Each open stream keeps its overlap-save tail and

@@ -119,6 +119,15 @@ def lib():
     for name in ("lp_beamform", "lp_dedisperse", "lp_synthesize",
                  "lp_trigger"):
         getattr(L, name).restype = i32
+    L.lp_plain_work_bytes.argtypes = [i32, i32, i32, i64]
+    L.lp_plain_work_bytes.restype = C.c_size_t
+    L.lp_dedisperse_plain.argtypes = [vp, C.POINTER(lp_band),
+                                      C.POINTER(C.c_double), i32, vp, i32,
+                                      i64, vp, i32, vp, vp, C.c_size_t, vp]
+    L.lp_synthesize_plain.argtypes = [vp, C.POINTER(lp_band), vp, i32, i64,
+                                      i64, vp, vp, vp, vp, C.c_size_t, vp]
+    L.lp_dedisperse_plain.restype = i32
+    L.lp_synthesize_plain.restype = i32
     sp = C.POINTER(lp_stream_cfg)
     L.lp_stream_resident_bytes.argtypes = [sp, i64]
     L.lp_stream_resident_bytes.restype = C.c_size_t
@@ -151,7 +160,8 @@ def exported_symbols():
             "lp_beam_bytes", "lp_dd_state_bytes", "lp_dd_bytes",
             "lp_syn_state_bytes", "lp_cand_bytes", "lp_trigger_work_bytes",
             "lp_beamform", "lp_dedisperse", "lp_synthesize", "lp_trigger",
-            "lp_stream_resident_bytes", "lp_block_bytes", "lp_server_create",
+            "lp_plain_work_bytes", "lp_dedisperse_plain",
+            "lp_synthesize_plain", "lp_stream_resident_bytes", "lp_block_bytes", "lp_server_create",
             "lp_server_create_sim", "lp_stream_open", "lp_stream_submit",
             "lp_stream_poll", "lp_stream_close", "lp_server_destroy",
             "lp_server_stats"]
@@ -262,6 +272,24 @@ def trigger(ctx: Ctx, cand, n_beams: int, n_tec: int, n_t: int, frame0: int,
                            _ptr(work), _stream(stream)))
 
 
+def dedisperse_plain(ctx: Ctx, band: Band, tec, y, n_beams: int, n_t: int,
+                     tail, d, work, flags: int = 0, stream=None):
+    t = np.ascontiguousarray(np.atleast_1d(tec), dtype=np.float64)
+    check(lib().lp_dedisperse_plain(ctx.h, C.byref(band.c),
+                                    t.ctypes.data_as(C.POINTER(C.c_double)),
+                                    len(t), _ptr(y), n_beams, n_t, _ptr(tail),
+                                    flags, _ptr(d), _ptr(work), work.numel(),
+                                    _stream(stream)))
+
+
+def synthesize_plain(ctx: Ctx, band: Band, d, n_series: int, n_t: int,
+                     frame0: int, hist, cand, work, x_out=None, stream=None):
+    check(lib().lp_synthesize_plain(ctx.h, C.byref(band.c), _ptr(d), n_series,
+                                    n_t, frame0, _ptr(hist), _ptr(x_out),
+                                    _ptr(cand), _ptr(work), work.numel(),
+                                    _stream(stream)))
+
+
 def nbytes(name: str, *args) -> int:
     return int(getattr(lib(), name)(*args))
 
@@ -284,6 +312,7 @@ class Pipeline:
     k_sigma: float = 6.0
     trig_cap: int = 4096
     want_series: bool = False
+    plain: bool = False          # plain FP32 comparator stages
     device: str = "cuda:0"
     frame0: int = 0
     bufs: dict = field(default_factory=dict)
@@ -310,6 +339,10 @@ class Pipeline:
             best=torch.zeros(B, dtype=torch.int32, device=self.device),
             sigma=torch.zeros((B, J), dtype=torch.float32, device=self.device),
         )
+        if self.plain:
+            self.prec = LP_FP32
+            self.bufs["pwork"] = buf(nbytes("lp_plain_work_bytes", B, J, S,
+                                            n_t))
         if self.want_series:
             self.bufs["x_out"] = torch.empty((B * J, n_t * LP_M),
                                              dtype=torch.float32,
@@ -328,11 +361,22 @@ class Pipeline:
                  self.dtype, self.prec, self.bufs["y"], stream)
 
     def dedisperse(self, stream=None):
+        if self.plain:
+            return dedisperse_plain(self.ctx, self.band, self.tec,
+                                    self.bufs["y"], self.n_beams, self.n_t,
+                                    self.bufs["tail"], self.bufs["d"],
+                                    self.bufs["pwork"], 0, stream)
         dedisperse(self.ctx, self.band, self.tec, self.bufs["y"],
                    self.n_beams, self.n_t, self.bufs["tail"], self.bufs["d"],
                    0, stream)
 
     def synthesize(self, stream=None):
+        if self.plain:
+            return synthesize_plain(self.ctx, self.band, self.bufs["d"],
+                                    self.n_beams * self.n_tec, self.n_t,
+                                    self.frame0, self.bufs["hist"],
+                                    self.bufs["cand"], self.bufs["pwork"],
+                                    self.bufs.get("x_out"), stream)
         synthesize(self.ctx, self.band, self.bufs["d"],
                    self.n_beams * self.n_tec, self.n_t, self.frame0,
                    self.bufs["hist"], self.bufs["cand"],

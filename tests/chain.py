@@ -26,13 +26,15 @@ def as_complex(t):
     return a[..., 0].astype(np.float64) + 1j * a[..., 1].astype(np.float64)
 
 
-def gpu_pipeline(blk, prec, n_t=None, want_series=True, tec=None, device="cuda:0"):
+def gpu_pipeline(blk, prec, n_t=None, want_series=True, tec=None,
+                 device="cuda:0", plain=False):
     n_t = n_t or blk.n_t
     ctx = lp.Ctx(0)
     p = lp.Pipeline(ctx, lp.Array(blk.enu, 2), lp.Band(blk.k), lp.Dirs(blk.az_el),
                     blk.tec if tec is None else tec, n_t,
                     dtype=lp.LP_CI8 if blk.x.dtype == np.int8 else lp.LP_CI16,
-                    prec=prec, want_series=want_series, device=device)
+                    prec=prec, want_series=want_series, device=device,
+                    plain=plain)
     return ctx, p
 
 
@@ -41,11 +43,11 @@ def to_device(x, device="cuda:0"):
     return torch.from_numpy(np.ascontiguousarray(x)).to(device)
 
 
-def run_gpu(blk, prec, want_series=True, blocks=None):
+def run_gpu(blk, prec, want_series=True, blocks=None, plain=False):
     """Run the chain over consecutive blocks (default: the whole block)."""
     import torch
     ctx, p = gpu_pipeline(blk, prec, n_t=blocks or blk.n_t,
-                          want_series=want_series)
+                          want_series=want_series, plain=plain)
     xs = [blk.x] if blocks is None else [
         blk.x[:, i:i + blocks] for i in range(0, blk.n_t, blocks)]
     outs = []

@@ -172,6 +172,25 @@ def test_determinism_bitwise():
     assert np.array_equal(a["trig"], b["trig"])
 
 
+@pytest.mark.parametrize("case", ["c1", "c2s"])
+def test_plain_fp32_comparator(case):
+    """The plain comparator pipeline matches the oracle at FP32 accuracy
+    and agrees with the fused pipeline."""
+    if case == "c1":
+        blk = lofarsim.generate(lofarsim.get_config("c1"))
+    else:
+        blk = lofarsim.generate(lofarsim.get_config("c2", n_t=4096,
+                                                    k=tuple(range(52, 116))))
+    g = run_gpu(blk, lp.LP_FP32, plain=True, blocks=blk.n_t // 2)
+    f = run_gpu(blk, lp.LP_FP32, blocks=blk.n_t // 2)
+    oc = OracleChain(blk)
+    for i, half in enumerate((blk.x[:, :blk.n_t // 2], blk.x[:, blk.n_t // 2:])):
+        o = oc.process(np.ascontiguousarray(half), keep_series=(0,))
+        _check_block(g[i], o, lp.LP_FP32, label=f"plain {case} block {i}",
+                     frame0=i * blk.n_t // 2)
+        assert rel_rms(g[i]["x"][0], f[i]["x"][0]) <= 1e-5
+
+
 def test_invalid_arguments_rejected():
     import torch
     from chain import gpu_pipeline
