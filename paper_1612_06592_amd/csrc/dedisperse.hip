@@ -22,9 +22,42 @@ constexpr int kDdLds = 4096 + 256;  // pad16 of 4095 is 4350
 
 // 4096-point transform of v[r] = in[j + 256 r] (j = thread); on return
 // v[r] = out[j + 256 r].  Unnormalised; INV selects exp(+2 pi i ...).
+// Twiddles exp(-2 pi i n / 4096) from two small LDS tables:
+// coarse[c] = w^(16 c) (c < 256), fine[f] = w^f (f < 16).
+template <bool INV>
+__device__ __forceinline__ float2 tw4096_lds(const float2 *coarse,
+                                             const float2 *fine, int n) {
+  float2 w = cmul(coarse[(n >> 4) & 255], fine[n & 15]);
+  return INV ? make_float2(w.x, -w.y) : w;
+}
+
+// v[r] *= w^r (r = 1..15), the powers formed by a product tree of depth 4
+// and each used as soon as it exists (few live registers, short chains).
+__device__ __forceinline__ void pow16_twiddle(float2 *v, const float2 w1) {
+  const float2 w2 = cmul(w1, w1), w4 = cmul(w2, w2), w8 = cmul(w4, w4);
+  const float2 w3 = cmul(w2, w1);
+  v[1] = cmul(v[1], w1);
+  v[2] = cmul(v[2], w2);
+  v[3] = cmul(v[3], w3);
+  v[4] = cmul(v[4], w4);
+  v[5] = cmul(v[5], cmul(w4, w1));
+  v[6] = cmul(v[6], cmul(w4, w2));
+  const float2 w7 = cmul(w4, w3);
+  v[7] = cmul(v[7], w7);
+  v[8] = cmul(v[8], w8);
+  v[9] = cmul(v[9], cmul(w8, w1));
+  v[10] = cmul(v[10], cmul(w8, w2));
+  v[11] = cmul(v[11], cmul(w8, w3));
+  v[12] = cmul(v[12], cmul(w8, w4));
+  v[13] = cmul(v[13], cmul(w8, cmul(w4, w1)));
+  v[14] = cmul(v[14], cmul(w8, cmul(w4, w2)));
+  v[15] = cmul(v[15], cmul(w8, w7));
+}
+
 template <bool INV>
 __device__ __forceinline__ void fft4096(float2 *v, float2 *lds,
-                                        const float2 *__restrict__ tw, int j) {
+                                        const float2 *coarse,
+                                        const float2 *fine, int j) {
   // Pass 0 (Ns = 1): no twiddle; write to (16 j + r).
   dft16<INV>(v);
   __syncthreads();
@@ -34,7 +67,10 @@ __device__ __forceinline__ void fft4096(float2 *v, float2 *lds,
   // Pass 1 (Ns = 16).
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = lds[pad16(j + 256 * r)];
-  twiddle16<INV>(v, tw, (j & 15) * 16);
+  {
+    const float2 w = coarse[j & 15];  // angle 2 pi (j mod 16) / 256
+    pow16_twiddle(v, INV ? make_float2(w.x, -w.y) : w);
+  }
   dft16<INV>(v);
   __syncthreads();
   {
@@ -46,7 +82,7 @@ __device__ __forceinline__ void fft4096(float2 *v, float2 *lds,
   // Pass 2 (Ns = 256): output index j + 256 r stays in registers.
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = lds[pad16(j + 256 * r)];
-  twiddle16<INV>(v, tw, j);
+  pow16_twiddle(v, tw4096_lds<INV>(coarse, fine, j));
   dft16<INV>(v);
 }
 
@@ -58,6 +94,10 @@ __attribute__((amdgpu_waves_per_eu(4, 8))) void dd_kernel(
     const float *__restrict__ rfk, int n_sb, int n_tec, long n_t, int n_hop,
     long n_blocks) {
   __shared__ float2 lds[kDdLds];
+  __shared__ float2 coarse[256], fine[16];
+  coarse[threadIdx.x] = tw[16 * threadIdx.x];
+  if (threadIdx.x < 16) fine[threadIdx.x] = tw[threadIdx.x];
+  // (the barrier inside the first transform orders these before use)
   const long bid = xcd_remap(blockIdx.x, n_blocks);
   const int h = (int)(bid % n_hop);
   const long bs = bid / n_hop;          // beam * n_sb + subband
@@ -75,7 +115,7 @@ __attribute__((amdgpu_waves_per_eu(4, 8))) void dd_kernel(
 #pragma unroll
   for (int r = 8; r < 16; ++r) v[r] = ys[hs + j + 256 * (r - 8)];
 
-  fft4096<false>(v, lds, tw, j);
+  fft4096<false>(v, lds, coarse, fine, j);
 
   // Hop 0 read the old tail above (and every thread has passed the
   // barriers inside the transform), so it can now store the new one.
@@ -108,7 +148,7 @@ __attribute__((amdgpu_waves_per_eu(4, 8))) void dd_kernel(
       v[r] = cmul(U[r], make_float2(cs, -sn));
     }
     __syncthreads();  // previous trial's last LDS reads are done
-    fft4096<true>(v, lds, tw, jo);
+    fft4096<true>(v, lds, coarse, fine, jo);
     float2 *out = d + (((long)b * n_tec + jt) * n_sb + s) * n_t + hs;
 #pragma unroll
     for (int r = 8; r < 16; ++r)

@@ -37,6 +37,7 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     SynCand *__restrict__ cand, float *__restrict__ psum, int n_sb, long n_t,
     long frame0, long warm, int F, long cand_nt, long cand_t0) {
   __shared__ float2 lds[16 * kSynFs];
+  __shared__ float2 tw1k[1024];   // exp(+2 pi i n / 1024)
   __shared__ float red_s[16];
 
   const int series = blockIdx.y;
@@ -54,6 +55,11 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
   float2 win[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) win[t] = make_float2(0.f, 0.f);
+  {
+    float2 w = tw[4 * tid];
+    tw1k[tid] = make_float2(w.x, -w.y);
+  }
+  // (the first barrier in the chunk loop orders these writes before use)
 
   const int n_chunk = F / 16;
   // Pass-0 inputs of a chunk: bins j + 64 r (r < 8; bins >= 512 are empty)
@@ -105,7 +111,11 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
       float2 *fr = lds + fo * kSynFs;
 #pragma unroll
       for (int r = 0; r < 16; ++r) v[r] = fr[pad16(jo + 64 * r)];
-      twiddle16<true>(v, tw, (jo & 15) * 16);
+      {
+        const int jm = (jo & 15) * 4;  // angle 2 pi (j mod 16) r / 256
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw1k[(jm * r) & 1023]);
+      }
       dft16<true>(v);
       __syncthreads();
       int base = (jo >> 4) * 256 + (jo & 15);
@@ -122,10 +132,9 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
         int jj = jo + 64 * q, jt = jj;
         float2 a0 = fr[pad16(jj)], a1 = fr[pad16(jj + 256)],
                a2 = fr[pad16(jj + 512)], a3 = fr[pad16(jj + 768)];
-        const float2 w1 = twiddle<true>(tw, jt * 4), w2 = cmul(w1, w1);
-        a1 = cmul(a1, w1);
-        a2 = cmul(a2, w2);
-        a3 = cmul(a3, cmul(w2, w1));
+        a1 = cmul(a1, tw1k[jt]);
+        a2 = cmul(a2, tw1k[2 * jt]);
+        a3 = cmul(a3, tw1k[(3 * jt) & 1023]);
         dft4<true>(a0, a1, a2, a3);
         fr[pad16(jj)] = a0;
         fr[pad16(jj + 256)] = a1;
