@@ -287,49 +287,77 @@ __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
 
 // --------------------------------------------------------- FP32 kernel
 
-// Grid: x = time tiles of T = 256 / G rows, y = subband.  Thread (t, g)
-// forms beams g, g + G, ... for time t from the LDS-staged tile.
+constexpr int kBf32Group = 8;  // beams accumulated per pass over a row
+
+// Grid: x = tiles of T = 256 / G time rows, y = subband.  The tile's raw
+// integer samples are staged in LDS with a row stride that is an odd
+// number of 32-bit words (conflict-free row-per-lane reads); the weights
+// [K][B] follow.  Thread (t, g) forms beams 8g .. 8g + 7, 8(g + G) .. for
+// time row t, eight beams per pass over the row.
 template <typename IT, int VB>
 __global__ __launch_bounds__(kBfThreads) void bf_fp32_kernel(
     const IT *__restrict__ x, const float2 *__restrict__ w,
     float2 *__restrict__ y, int n_sb, long n_t, long x_nt, int n_in,
-    int n_beams, int G) {
-  extern __shared__ float smf[];
+    int n_beams, int row_words, int G) {
+  extern __shared__ int smi[];
   const int T = kBfThreads / G;
-  const int RK = 2 * n_in, RKP = RK + 1;
-  float *xs = smf;
-  float2 *ws = reinterpret_cast<float2 *>(smf + ((T * RKP + 1) & ~1));
+  const int RK = 2 * n_in;
+  const int row_bytes = RK * (int)sizeof(IT);
+  int *xs = smi;                                        // [T][row_words]
+  float2 *ws = reinterpret_cast<float2 *>(smi + T * row_words);
   const int s = blockIdx.y;
   const long t0 = (long)blockIdx.x * T;
   const int rows = (int)min((long)T, n_t - t0);
-  constexpr int EPV = VB / (int)sizeof(IT);
   const char *base =
       reinterpret_cast<const char *>(x + ((long)s * x_nt + t0) * RK);
-  const int nvec = rows * RK / EPV;
+  const int vec_per_row = row_bytes / VB;
+  const int nvec = rows * vec_per_row;
   for (int v = threadIdx.x; v < nvec; v += kBfThreads) {
-    int e0 = v * EPV, row = e0 / RK, col = e0 - row * RK;
-    IT raw[EPV];
-    load_vec<VB>(raw, base + (size_t)v * VB);
+    int row = v / vec_per_row, c = v - row * vec_per_row;
+    int q[VB / 4];
+    __builtin_memcpy(q, base + (size_t)v * VB, VB);
 #pragma unroll
-    for (int i = 0; i < EPV; ++i) xs[row * RKP + col + i] = (float)raw[i];
+    for (int i = 0; i < VB / 4; ++i) xs[row * row_words + c * (VB / 4) + i] = q[i];
   }
   const float2 *wsrc = w + (long)s * n_in * n_beams;
   for (int i = threadIdx.x; i < n_in * n_beams; i += kBfThreads) ws[i] = wsrc[i];
   __syncthreads();
   const int t = threadIdx.x % T, g = threadIdx.x / T;
   if (t >= rows) return;
-  const float *xr = xs + t * RKP;
-  for (int b = g; b < n_beams; b += G) {
-    float ar = 0.f, ai = 0.f;
+  const int *xr = xs + t * row_words;
+  for (int b0 = kBf32Group * g; b0 < n_beams; b0 += kBf32Group * G) {
+    float ar[kBf32Group], ai[kBf32Group];
+#pragma unroll
+    for (int k = 0; k < kBf32Group; ++k) ar[k] = ai[k] = 0.f;
     for (int i = 0; i < n_in; ++i) {
-      float2 wv = ws[i * n_beams + b];
-      float re = xr[2 * i], im = xr[2 * i + 1];
-      ar = fmaf(re, wv.x, ar);
-      ar = fmaf(-im, wv.y, ar);
-      ai = fmaf(re, wv.y, ai);
-      ai = fmaf(im, wv.x, ai);
+      float re, im;
+      if constexpr (sizeof(IT) == 1) {
+        int word = xr[i >> 1];
+        int sh = (i & 1) * 16;
+        re = (float)(signed char)(word >> sh);
+        im = (float)(signed char)(word >> (sh + 8));
+      } else {
+        int word = xr[i];
+        re = (float)(short)(word & 0xffff);
+        im = (float)(short)(word >> 16);
+      }
+      const float2 *wi = ws + i * n_beams + b0;
+#pragma unroll
+      for (int k = 0; k < kBf32Group; ++k) {
+        if (b0 + k < n_beams) {
+          float2 wv = wi[k];
+          ar[k] = fmaf(re, wv.x, ar[k]);
+          ar[k] = fmaf(-im, wv.y, ar[k]);
+          ai[k] = fmaf(re, wv.y, ai[k]);
+          ai[k] = fmaf(im, wv.x, ai[k]);
+        }
+      }
     }
-    y[((long)b * n_sb + s) * n_t + t0 + t] = make_float2(ar, ai);
+#pragma unroll
+    for (int k = 0; k < kBf32Group; ++k)
+      if (b0 + k < n_beams)
+        y[((long)(b0 + k) * n_sb + s) * n_t + t0 + t] =
+            make_float2(ar[k], ai[k]);
   }
 }
 
@@ -483,13 +511,15 @@ static lp_status launch_bf(const BfPlan *p, const void *x, long x_nt,
 #undef LP_BF_PICK
     if (rc) return rc;
   } else {
-    int G = p->n_beams >= 4 ? 4 : p->n_beams >= 2 ? 2 : 1;
-    int T = kBfThreads / G;
+    int row_words = row_bytes / 4;
+    if (row_words % 2 == 0) row_words += 1;  // odd stride: no bank conflicts
+    // Rows per tile: 256, halved (with G = 256 / T threads sharing a row's
+    // beam groups) until the tile and the weights fit in LDS.
+    int T = kBfThreads, G = 1;
     auto lds = [&](int T_) {
-      return (((size_t)T_ * (RK + 1) + 1) & ~(size_t)1) * 4 +
-             (size_t)n_in * p->n_beams * 8;
+      return (size_t)T_ * row_words * 4 + (size_t)n_in * p->n_beams * 8;
     };
-    while (lds(T) > kLdsMax && T > 16) {
+    while (lds(T) > kLdsMax && T > 32) {
       T /= 2;
       G *= 2;
     }
@@ -504,7 +534,7 @@ static lp_status launch_bf(const BfPlan *p, const void *x, long x_nt,
       hipLaunchKernelGGL(kern, grid, dim3(kBfThreads), shm, st,
                          static_cast<const IT *>(x), p->w.as<const float2>(),
                          static_cast<float2 *>(y), n_sb, n_t, x_nt, n_in,
-                         p->n_beams, G);
+                         p->n_beams, row_words, G);
       return LP_OK;
     };
     lp_status rc = (vb == 16)  ? args(bf_fp32_kernel<IT, 16>)

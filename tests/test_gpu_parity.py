@@ -113,6 +113,30 @@ def test_beamform_61_beams_96_inputs():
         assert e <= TOL[prec]
 
 
+def test_beamform_largest_shape_ci16():
+    """The largest documented beamformer call: 128 inputs (64 stations x 2
+    pol), 64 beams, int16 samples; the FP32 tile is then halved to fit
+    LDS."""
+    cfg = lofarsim.get_config("c1", n_st=64, hex_rings=4, n_t=256,
+                              k=tuple(range(200, 206)), n_pulses=0)
+    blk = lofarsim.generate(cfg)
+    blk.az_el = np.concatenate([blk.az_el, blk.az_el[:3] + 0.001])
+    assert blk.az_el.shape[0] == 64 and blk.x.dtype == np.int16
+    import oracle
+    import torch
+    from chain import as_complex, gpu_pipeline, to_device
+    ref = oracle.beamform(blk.enu, 2, blk.k, blk.az_el, blk.x)
+    for prec in (lp.LP_FP16_MFMA, lp.LP_FP32):
+        print("case bf-max prec", prec, flush=True)
+        ctx, p = gpu_pipeline(blk, prec, want_series=False)
+        p.beamform(to_device(blk.x))
+        torch.cuda.synchronize()
+        e = rel_rms(as_complex(p.y_view()), ref)
+        ctx.close()
+        print("bf-max prec", prec, "rel-rms", e, flush=True)
+        assert e <= TOL[prec]
+
+
 def test_c4_slice_tec_grid():
     tec = tuple(np.linspace(0, 30, 32).tolist())
     cfg = lofarsim.get_config("c4", n_t=2048, k=tuple(range(52, 68)),
