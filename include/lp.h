@@ -163,7 +163,9 @@ size_t lp_trigger_work_bytes(int32_t n_beams, int32_t n_tec);
  *       to unit peak magnitude by a power of two that is moved, exactly, onto
  *       the input's samples (int8 and |int16| <= 2048 are exact in FP16).
  * Requires n_st * n_pol <= 128, n_beams <= 64 per call, n_t % 128 == 0, and
- * n_st * n_pol * sizeof(sample) a multiple of 4 bytes (else LP_EINVAL).   */
+ * a time row (n_st * n_pol complex samples) a multiple of 4 bytes; with
+ * LP_FP16_MFMA a row of at most 256 bytes (int16 samples: n_st * n_pol
+ * <= 64).  Else LP_EINVAL.                                                */
 lp_status lp_beamform(lp_ctx *ctx, const lp_array *array, const lp_band *band,
                       const lp_dir *beams, int32_t n_beams, const void *x,
                       int32_t dtype, int64_t n_t, int32_t prec, void *y,
@@ -229,6 +231,47 @@ lp_status lp_synthesize_plain(lp_ctx *ctx, const lp_band *band, const void *d,
                               int32_t n_series, int64_t n_t, int64_t frame0,
                               void *hist, float *x_out, void *cand, void *work,
                               size_t work_bytes, void *hip_stream);
+
+/* ---- PPF inversion by LSMR (Sec. 3, "Computing requirements") ---------- */
+/* The paper recovers the 5 ns signal by solving the sparse system H x = y
+ * for the filtered subband data with the iterative LSMR method (Fong &
+ * Saunders 2011), about 25 iterations.  H is the station's analysis
+ * polyphase filterbank (prototype h: Kaiser-windowed sinc, band->kaiser_beta,
+ * M = 1024, 16 taps) restricted to the subbands band->k:
+ *   y_s[m] = sum_{l < 16384} h[l] exp(+2 pi i k_s l / 1024) x[1024 m + 1023 - l]
+ * for output frames m = 0 .. n_frames - 1 of a real series x of
+ * F = n_frames - 15 frames (1024 F samples; zero outside), so frame m of y
+ * sees frames m - 15 .. m of x.
+ * Layouts (device memory, caller-owned): y and d are complex float
+ * [n_series][n_sb][n_frames] (the layout lp_dedisperse writes: series =
+ * beam * n_tec + trial); x is float [n_series][F * 1024], time order.
+ * n_frames in [16, 2^24].  All calls are asynchronous on hip_stream.       */
+
+/* y = H x (the analysis filterbank; also a station-PPF simulator).        */
+lp_status lp_ppf_analyze(lp_ctx *ctx, const lp_band *band, const float *x,
+                         int32_t n_series, int64_t n_frames, void *y,
+                         void *hip_stream);
+/* x = H^T y, the real adjoint (x real, y complex, inner product Re <a, b>). */
+lp_status lp_ppf_adjoint(lp_ctx *ctx, const lp_band *band, const void *y,
+                         int32_t n_series, int64_t n_frames, float *x,
+                         void *hip_stream);
+/* Workspace of lp_ppf_invert (0 on invalid sizes).                         */
+size_t lp_ppf_work_bytes(int32_t n_sb, int32_t n_series, int64_t n_frames);
+/* n_iter LSMR iterations from x_0 = 0 with no damping, per series, in FP32
+ * vectors with FP64 scalar recurrences; stops changing x once the
+ * bidiagonalisation ends (alpha or beta zero; y = 0 gives x = 0).
+ *   x      out, [n_series][F * 1024]
+ *   anorm  out or NULL, double [n_series][n_iter + 1]: ||H^T r_k|| for
+ *          k = 0 .. n_iter as LSMR's recurrence gives it (|zetabar_{k+1}|)
+ *   rnorm  out or NULL, double [n_series]: ||y - H x|| computed from x
+ *          (one more application of H)
+ *   work   device, >= lp_ppf_work_bytes(), 256-byte aligned; no state is
+ *          kept in it between calls.
+ * LP_EINVAL on NULL or misaligned buffers, bad sizes or a short workspace. */
+lp_status lp_ppf_invert(lp_ctx *ctx, const lp_band *band, const void *y,
+                        int32_t n_series, int64_t n_frames, int32_t n_iter,
+                        float *x, double *anorm, double *rnorm, void *work,
+                        size_t work_bytes, void *hip_stream);
 
 /* ---- serving: concurrent observation streams ------------------------- */
 /* A persistent request loop (one host thread) runs the four stages for many

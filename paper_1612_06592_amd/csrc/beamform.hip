@@ -562,8 +562,6 @@ extern "C" lp_status lp_beamform(lp_ctx *ctx, const lp_array *array,
   if (array->n_st <= 0 || array->n_pol <= 0 || !array->enu_m)
     return set_error(LP_EINVAL, "lp_beamform: bad array descriptor");
   const int n_in = array->n_st * array->n_pol;
-  if (n_in > 128)
-    return set_error(LP_EINVAL, "lp_beamform: n_st*n_pol = %d > 128", n_in);
   if (n_beams <= 0 || n_beams > 64)
     return set_error(LP_EINVAL, "lp_beamform: n_beams %d not in 1..64",
                      n_beams);
@@ -574,9 +572,8 @@ extern "C" lp_status lp_beamform(lp_ctx *ctx, const lp_array *array,
   if (n_t <= 0 || n_t % kBfT != 0)
     return set_error(LP_EINVAL, "lp_beamform: n_t %lld not a multiple of %d",
                      (long long)n_t, kBfT);
-  if ((2 * n_in * (dtype == LP_CI8 ? 1 : 2)) % 4 != 0)
-    return set_error(LP_EINVAL,
-                     "lp_beamform: a time row must be a multiple of 4 bytes");
+  if (const char *why = bf_shape_error(n_in, dtype, prec))
+    return set_error(LP_EINVAL, "lp_beamform: %s (n_in %d)", why, n_in);
   if (reinterpret_cast<uintptr_t>(x) % 16 || reinterpret_cast<uintptr_t>(y) % 16)
     return set_error(LP_EINVAL, "lp_beamform: x and y must be 16-byte aligned");
   if ((rc = set_device(ctx))) return rc;

@@ -174,6 +174,10 @@ lp_status get_syn_plan(lp_ctx *ctx, const lp_band *band, SynPlan **out) {
   LP_HIP(hipMalloc(&p->binmap.p, 512 * 2));
   LP_HIP(hipMemcpy(p->taps.p, g32.data(), L * 4, hipMemcpyHostToDevice));
   LP_HIP(hipMemcpy(p->binmap.p, bm.data(), 512 * 2, hipMemcpyHostToDevice));
+  std::vector<int16_t> kb(band->n_sb);
+  for (int i = 0; i < band->n_sb; ++i) kb[i] = (int16_t)band->k[i];
+  LP_HIP(hipMalloc(&p->kbin.p, band->n_sb * 2));
+  LP_HIP(hipMemcpy(p->kbin.p, kb.data(), band->n_sb * 2, hipMemcpyHostToDevice));
   *out = p.get();
   ctx->syn.push_back(std::move(p));
   return LP_OK;

@@ -70,6 +70,7 @@ struct SynPlan {
   std::vector<uint8_t> key;
   DevBuf taps;    // f32 [16][1024] g = M h
   DevBuf binmap;  // i16 [512] subband position of bin k, or -1
+  DevBuf kbin;    // i16 [n_sb] bin k of each subband position
 };
 
 }  // namespace lp
@@ -84,6 +85,20 @@ struct lp_ctx {
 };
 
 namespace lp {
+
+// Beamformer input shapes every launch supports: at most 128 inputs, a
+// time row (n_in complex samples) a multiple of 4 bytes, and on the
+// FP16-MFMA path a row of at most 256 bytes (the kernel's staging tile).
+// Returns NULL when supported, else the reason.
+inline const char *bf_shape_error(int n_in, int dtype, int prec) {
+  if (n_in <= 0 || n_in > 128) return "n_st * n_pol must be in 1..128";
+  const int row = 2 * n_in * (dtype == LP_CI8 ? 1 : 2);
+  if (row % 4 != 0) return "a time row must be a multiple of 4 bytes";
+  if (prec == LP_FP16_MFMA && row > 256)
+    return "FP16-MFMA needs time rows of at most 256 bytes "
+           "(int16 samples: at most 64 inputs)";
+  return nullptr;
+}
 
 // Plan lookups (create on first use; creation is synchronous).
 lp_status get_bf_plan(lp_ctx *ctx, const lp_array *a, const lp_band *band,

@@ -493,6 +493,9 @@ static lp_status check_cfg(const lp_stream_cfg *c) {
     return set_error(LP_EINVAL, "stream cfg: dtype");
   if (c->prec != LP_FP32 && c->prec != LP_FP16_MFMA)
     return set_error(LP_EINVAL, "stream cfg: precision");
+  if (const char *why = bf_shape_error(c->array.n_st * c->array.n_pol,
+                                       c->dtype, c->prec))
+    return set_error(LP_EINVAL, "stream cfg: %s", why);
   if (c->max_n_t <= 0 || c->max_n_t % kHop)
     return set_error(LP_EINVAL, "stream cfg: max_n_t must be a multiple of %d",
                      kHop);

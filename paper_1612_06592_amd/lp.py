@@ -128,6 +128,14 @@ def lib():
                                       i64, vp, vp, vp, vp, C.c_size_t, vp]
     L.lp_dedisperse_plain.restype = i32
     L.lp_synthesize_plain.restype = i32
+    L.lp_ppf_analyze.argtypes = [vp, C.POINTER(lp_band), vp, i32, i64, vp, vp]
+    L.lp_ppf_adjoint.argtypes = [vp, C.POINTER(lp_band), vp, i32, i64, vp, vp]
+    L.lp_ppf_work_bytes.argtypes = [i32, i32, i64]
+    L.lp_ppf_work_bytes.restype = C.c_size_t
+    L.lp_ppf_invert.argtypes = [vp, C.POINTER(lp_band), vp, i32, i64, i32,
+                                vp, vp, vp, vp, C.c_size_t, vp]
+    for name in ("lp_ppf_analyze", "lp_ppf_adjoint", "lp_ppf_invert"):
+        getattr(L, name).restype = i32
     sp = C.POINTER(lp_stream_cfg)
     L.lp_stream_resident_bytes.argtypes = [sp, i64]
     L.lp_stream_resident_bytes.restype = C.c_size_t
@@ -161,10 +169,11 @@ def exported_symbols():
             "lp_syn_state_bytes", "lp_cand_bytes", "lp_trigger_work_bytes",
             "lp_beamform", "lp_dedisperse", "lp_synthesize", "lp_trigger",
             "lp_plain_work_bytes", "lp_dedisperse_plain",
-            "lp_synthesize_plain", "lp_stream_resident_bytes", "lp_block_bytes", "lp_server_create",
-            "lp_server_create_sim", "lp_stream_open", "lp_stream_submit",
-            "lp_stream_poll", "lp_stream_close", "lp_server_destroy",
-            "lp_server_stats"]
+            "lp_synthesize_plain", "lp_ppf_analyze", "lp_ppf_adjoint",
+            "lp_ppf_work_bytes", "lp_ppf_invert", "lp_stream_resident_bytes",
+            "lp_block_bytes", "lp_server_create", "lp_server_create_sim",
+            "lp_stream_open", "lp_stream_submit", "lp_stream_poll",
+            "lp_stream_close", "lp_server_destroy", "lp_server_stats"]
 
 
 def check(rc: int):
@@ -288,6 +297,32 @@ def synthesize_plain(ctx: Ctx, band: Band, d, n_series: int, n_t: int,
                                     n_t, frame0, _ptr(hist), _ptr(x_out),
                                     _ptr(cand), _ptr(work), work.numel(),
                                     _stream(stream)))
+
+
+def ppf_analyze(ctx: Ctx, band: Band, x, n_series: int, n_frames: int, y,
+                stream=None):
+    """y = H x: x float [n_series][(n_frames - 15) * 1024] -> y complex
+    float [n_series][n_sb][n_frames] (trailing dim 2 for re, im)."""
+    check(lib().lp_ppf_analyze(ctx.h, C.byref(band.c), _ptr(x), n_series,
+                               n_frames, _ptr(y), _stream(stream)))
+
+
+def ppf_adjoint(ctx: Ctx, band: Band, y, n_series: int, n_frames: int, x,
+                stream=None):
+    """x = H^T y (shapes as in ppf_analyze)."""
+    check(lib().lp_ppf_adjoint(ctx.h, C.byref(band.c), _ptr(y), n_series,
+                               n_frames, _ptr(x), _stream(stream)))
+
+
+def ppf_invert(ctx: Ctx, band: Band, y, n_series: int, n_frames: int,
+               n_iter: int, x, work, anorm=None, rnorm=None, stream=None):
+    """n_iter LSMR iterations on H x = y per series (x, y as in
+    ppf_analyze); anorm double [n_series][n_iter + 1], rnorm double
+    [n_series] (optional); work uint8 of lp_ppf_work_bytes()."""
+    check(lib().lp_ppf_invert(ctx.h, C.byref(band.c), _ptr(y), n_series,
+                              n_frames, n_iter, _ptr(x), _ptr(anorm),
+                              _ptr(rnorm), _ptr(work), work.numel(),
+                              _stream(stream)))
 
 
 def nbytes(name: str, *args) -> int:

@@ -113,11 +113,15 @@ def test_beamform_61_beams_96_inputs():
         assert e <= TOL[prec]
 
 
-def test_beamform_largest_shape_ci16():
-    """The largest documented beamformer call: 128 inputs (64 stations x 2
-    pol), 64 beams, int16 samples; the FP32 tile is then halved to fit
-    LDS."""
-    cfg = lofarsim.get_config("c1", n_st=64, hex_rings=4, n_t=256,
+@pytest.mark.parametrize("n_st,precs", [
+    (64, (lp.LP_FP32,)),                     # 128 inputs: 512-byte rows
+    (32, (lp.LP_FP16_MFMA, lp.LP_FP32)),     # 64 inputs: the MFMA maximum
+])
+def test_beamform_largest_shapes_ci16(n_st, precs):
+    """The largest documented beamformer calls with int16 samples and 64
+    beams: 128 inputs on the FP32 path (its tile is halved to fit LDS; the
+    MFMA path rejects 512-byte rows with LP_EINVAL), 64 inputs on both."""
+    cfg = lofarsim.get_config("c1", n_st=n_st, hex_rings=4, n_t=256,
                               k=tuple(range(200, 206)), n_pulses=0)
     blk = lofarsim.generate(cfg)
     blk.az_el = np.concatenate([blk.az_el, blk.az_el[:3] + 0.001])
@@ -126,8 +130,8 @@ def test_beamform_largest_shape_ci16():
     import torch
     from chain import as_complex, gpu_pipeline, to_device
     ref = oracle.beamform(blk.enu, 2, blk.k, blk.az_el, blk.x)
-    for prec in (lp.LP_FP16_MFMA, lp.LP_FP32):
-        print("case bf-max prec", prec, flush=True)
+    for prec in precs:
+        print("case bf-max n_st", n_st, "prec", prec, flush=True)
         ctx, p = gpu_pipeline(blk, prec, want_series=False)
         p.beamform(to_device(blk.x))
         torch.cuda.synchronize()
@@ -135,6 +139,11 @@ def test_beamform_largest_shape_ci16():
         ctx.close()
         print("bf-max prec", prec, "rel-rms", e, flush=True)
         assert e <= TOL[prec]
+    if n_st == 64:
+        ctx, p = gpu_pipeline(blk, lp.LP_FP16_MFMA, want_series=False)
+        with pytest.raises(lp.LpError, match="256 bytes"):
+            p.beamform(to_device(blk.x))
+        ctx.close()
 
 
 def test_c4_slice_tec_grid():

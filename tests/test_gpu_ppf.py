@@ -1,0 +1,234 @@
+"""PPF inversion on the GPU (lp_ppf_analyze, lp_ppf_adjoint, lp_ppf_invert)
+against the FP64 oracle (oracle/ppf_lsmr.py).
+
+Tolerances: H and H^T are FP32 transforms and FIRs whose relative RMS error
+is a few 1e-7; 1e-5 is asserted.  LSMR's iterates after 25 iterations in
+FP32 vectors (FP64 scalars) against the FP64 iterates: 1e-3 relative RMS,
+the path's stated bound; the per-iteration ||H^T r_k|| to 1e-3 as well.
+
+At full size (C2's 244 subbands, 65536 frames, one series) the oracle
+cannot run LSMR in seconds, so: H and H^T are compared on sampled frames
+(each needs only 16 frames of its input), and the solve is checked by
+properties that hold at any size: the returned ||y - H x|| and ||H^T r||
+equal the ones recomputed with the library's own H and H^T, and a signal in
+the row space of H (x = H^T z) is recovered as LSMR recovers it in the
+oracle at the same iteration count.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import ppf_lsmr as pl
+from paper_1612_06592_amd import lp
+
+pytestmark = pytest.mark.gpu
+
+M, P = 1024, 16
+K_C2 = np.arange(52, 296)
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.sqrt(np.sum(np.abs(a - b) ** 2) / np.sum(np.abs(b) ** 2)))
+
+
+def _to_dev_c(y):
+    import torch
+    a = np.stack([y.real, y.imag], -1).astype(np.float32)
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _from_dev_c(t):
+    a = t.cpu().numpy().astype(np.float64)
+    return a[..., 0] + 1j * a[..., 1]
+
+
+def _analyze(ctx, band, x, ns, nf):
+    import torch
+    xd = torch.from_numpy(np.ascontiguousarray(x, np.float32)).to("cuda:0")
+    y = torch.empty((ns, band.n_sb, nf, 2), dtype=torch.float32, device="cuda:0")
+    lp.ppf_analyze(ctx, band, xd, ns, nf, y)
+    torch.cuda.synchronize()
+    return _from_dev_c(y)
+
+
+def _adjoint(ctx, band, y, ns, nf):
+    import torch
+    x = torch.empty((ns, (nf - P + 1) * M), dtype=torch.float32, device="cuda:0")
+    lp.ppf_adjoint(ctx, band, _to_dev_c(y), ns, nf, x)
+    torch.cuda.synchronize()
+    return x.cpu().numpy().astype(np.float64)
+
+
+def _invert(ctx, band, y_dev, ns, nf, n_iter):
+    import torch
+    x = torch.empty((ns, (nf - P + 1) * M), dtype=torch.float32, device="cuda:0")
+    wb = lp.nbytes("lp_ppf_work_bytes", band.n_sb, ns, nf)
+    work = torch.empty(wb, dtype=torch.uint8, device="cuda:0")
+    an = torch.empty((ns, n_iter + 1), dtype=torch.float64, device="cuda:0")
+    rn = torch.empty(ns, dtype=torch.float64, device="cuda:0")
+    lp.ppf_invert(ctx, band, y_dev, ns, nf, n_iter, x, work, an, rn)
+    torch.cuda.synchronize()
+    return x, an.cpu().numpy(), rn.cpu().numpy()
+
+
+def test_analysis_and_adjoint_match_oracle():
+    """Two series, 600 frames: three forward and three adjoint workgroups
+    per series with a ragged last one."""
+    ns, nf = 2, 600
+    F = nf - P + 1
+    rng = np.random.default_rng(5)
+    h = oracle.prototype(M, P, 9.0)
+    band = lp.Band(K_C2)
+    ctx = lp.Ctx(0)
+    x = rng.standard_normal((ns, F * M))
+    print("case ppf H/H^T ns=2 nf=600", flush=True)
+    yg = _analyze(ctx, band, x, ns, nf)
+    for q in range(ns):
+        e = _rel(yg[q], pl.analysis(h, M, K_C2, x[q]))
+        print(f"H series {q} rel-rms {e:.2e}", flush=True)
+        assert e <= 1e-5
+    y = rng.standard_normal((ns, len(K_C2), nf)) + \
+        1j * rng.standard_normal((ns, len(K_C2), nf))
+    xg = _adjoint(ctx, band, y, ns, nf)
+    for q in range(ns):
+        e = _rel(xg[q], pl.adjoint(h, M, K_C2, y[q]))
+        print(f"H^T series {q} rel-rms {e:.2e}", flush=True)
+        assert e <= 1e-5
+    # Dot-product test of the GPU pair.
+    a = np.real(np.vdot(yg[0], y[0]))
+    b = np.dot(x[0], xg[0])
+    assert abs(a - b) <= 1e-5 * np.sqrt(np.sum(np.abs(yg[0]) ** 2) *
+                                       np.sum(np.abs(y[0]) ** 2))
+    ctx.close()
+
+
+def test_invert_matches_oracle_lsmr():
+    """Series 0: y = H x + noise (inconsistent); series 1: zero (x = 0);
+    series 2: y in the range of H.  25 iterations."""
+    import torch
+    ns, nf, it = 3, 600, 25
+    F = nf - P + 1
+    rng = np.random.default_rng(9)
+    h = oracle.prototype(M, P, 9.0)
+    k = np.arange(100, 180)
+    band = lp.Band(k)
+    x0 = rng.standard_normal(F * M)
+    y = np.zeros((ns, len(k), nf), complex)
+    y[0] = pl.analysis(h, M, k, x0) + 0.05 * (
+        rng.standard_normal((len(k), nf)) + 1j * rng.standard_normal((len(k), nf)))
+    y[2] = pl.analysis(h, M, k, pl.adjoint(h, M, k, rng.standard_normal(
+        (len(k), nf)) + 1j * rng.standard_normal((len(k), nf))))
+    ctx = lp.Ctx(0)
+    print("case ppf invert ns=3 nf=600 iters=25", flush=True)
+    xg, an, rn = _invert(ctx, band, _to_dev_c(y), ns, nf, it)
+    xg = xg.cpu().numpy().astype(np.float64)
+    for q in (0, 2):
+        xo, ao = pl.invert(h, M, k, y[q], it)
+        e = _rel(xg[q], xo)
+        ea = np.max(np.abs(an[q] - ao) / ao[0])
+        r = np.linalg.norm(y[q] - pl.analysis(h, M, k, xo))
+        er = abs(rn[q] - r) / np.linalg.norm(y[q])
+        print(f"series {q}: x rel-rms {e:.2e}, anorm max rel {ea:.2e}, "
+              f"rnorm {rn[q]:.4e} vs {r:.4e}", flush=True)
+        assert e <= 1e-3
+        assert ea <= 1e-3
+        assert er <= 1e-4
+    assert not np.any(xg[1]) and not np.any(an[1]) and rn[1] == 0.0
+    ctx.close()
+    del xg
+    torch.cuda.empty_cache()
+
+
+def test_invert_edge_cases():
+    import torch
+    rng = np.random.default_rng(2)
+    h = oracle.prototype(M, P, 9.0)
+    k = np.arange(60, 70)
+    band = lp.Band(k)
+    ctx = lp.Ctx(0)
+    # The shortest block: 16 frames (one unknown frame), 7 iterations.
+    nf = 16
+    y = rng.standard_normal((1, len(k), nf)) + 1j * rng.standard_normal((1, len(k), nf))
+    print("case ppf invert nf=16", flush=True)
+    xg, an, rn = _invert(ctx, band, _to_dev_c(y), 1, nf, 7)
+    xo, ao = pl.invert(h, M, k, y[0], 7)
+    assert _rel(xg.cpu().numpy()[0], xo) <= 1e-3
+    # No iteration: x = 0 and anorm[0] = ||H^T y||.
+    print("case ppf invert n_iter=0", flush=True)
+    xg, an, rn = _invert(ctx, band, _to_dev_c(y), 1, nf, 0)
+    assert not np.any(xg.cpu().numpy())
+    ref = np.linalg.norm(pl.adjoint(h, M, k, y[0]))
+    assert abs(an[0, 0] - ref) <= 1e-5 * ref
+    assert abs(rn[0] - np.linalg.norm(y[0])) <= 1e-5 * np.linalg.norm(y[0])
+    # Invalid arguments are rejected before any launch.
+    yd = _to_dev_c(y)
+    x = torch.empty(M, dtype=torch.float32, device="cuda:0")
+    w = torch.empty(lp.nbytes("lp_ppf_work_bytes", len(k), 1, nf),
+                    dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(lp.LpError):
+        lp.ppf_invert(ctx, band, yd, 1, 15, 5, x, w)          # n_frames < 16
+    with pytest.raises(lp.LpError):
+        lp.ppf_invert(ctx, band, yd, 1, nf, 5, x, w[:-256])   # short work
+    with pytest.raises(lp.LpError):
+        lp.ppf_invert(ctx, band, yd, 1, nf, -1, x, w)         # n_iter < 0
+    ctx.close()
+
+
+def test_full_size_c2_band():
+    """C2's band and block length (244 subbands, 65536 frames), one series."""
+    import torch
+    nf, it = 65536, 25
+    F = nf - P + 1
+    h = oracle.prototype(M, P, 9.0)
+    band = lp.Band(K_C2)
+    ctx = lp.Ctx(0)
+    rng = np.random.default_rng(13)
+    g = torch.Generator(device="cuda:0").manual_seed(13)
+    z = torch.randn((1, len(K_C2), nf, 2), generator=g, device="cuda:0")
+    xt = torch.empty((1, F * M), dtype=torch.float32, device="cuda:0")
+    lp.ppf_adjoint(ctx, band, z, 1, nf, xt)           # x_true = H^T z
+    y = torch.empty_like(z)
+    lp.ppf_analyze(ctx, band, xt, 1, nf, y)           # y = H x_true
+    torch.cuda.synchronize()
+    # H^T and H on sampled frames against the oracle (each output frame
+    # needs 16 frames of input).
+    zc = _from_dev_c(z[0])
+    xtn = xt[0].cpu().numpy().astype(np.float64)
+    yc = _from_dev_c(y[0])
+    for j0 in (0, 31000, F - 40):
+        w = zc[:, j0:j0 + 40 + P - 1]
+        ref = pl.adjoint(h, M, K_C2, w)
+        got = xtn[j0 * M:(j0 + 40) * M]
+        assert _rel(got, ref) <= 1e-5, j0
+    for m0 in (0, 40000, nf - 40):
+        lo = max(0, m0 - (P - 1))
+        seg = xtn[lo * M:min(F, m0 + 40) * M]
+        ref = pl.analysis(h, M, K_C2, seg)[:, m0 - lo:m0 - lo + 40]
+        assert _rel(yc[:, m0:m0 + 40], ref) <= 1e-5, m0
+    print("case ppf invert full C2 band, 25 iterations", flush=True)
+    x, an, rn = _invert(ctx, band, y, 1, nf, it)
+    # Returned norms agree with the library's own operators.
+    yx = torch.empty_like(y)
+    lp.ppf_analyze(ctx, band, x, 1, nf, yx)
+    r = (y - yx)
+    atr = torch.empty_like(xt)
+    lp.ppf_adjoint(ctx, band, r, 1, nf, atr)
+    torch.cuda.synchronize()
+    r_true = float(torch.linalg.vector_norm(r.double()))
+    atr_true = float(torch.linalg.vector_norm(atr.double()))
+    ynorm = float(torch.linalg.vector_norm(y.double()))
+    err = float(torch.linalg.vector_norm((x - xt).double()) /
+                torch.linalg.vector_norm(xt.double()))
+    print(f"full: ||r||/||y|| {rn[0] / ynorm:.3e} (recomputed "
+          f"{r_true / ynorm:.3e}); ||H^T r|| {an[0, -1]:.4e} (recomputed "
+          f"{atr_true:.4e}); x error {err:.3e}; anorm[0..5] "
+          f"{np.round(an[0, :6] / an[0, 0], 5).tolist()}", flush=True)
+    assert abs(rn[0] - r_true) <= 1e-3 * r_true + 1e-6 * ynorm
+    assert abs(an[0, -1] - atr_true) <= 0.05 * atr_true
+    assert np.all(np.diff(an[0]) <= 0)
+    # The oracle reaches ||r||/||y|| < 2e-4 and x error < 3e-3 on the same
+    # construction at F = 24 in 25 iterations.
+    assert rn[0] / ynorm < 5e-4
+    assert err < 5e-3
+    ctx.close()

@@ -65,6 +65,16 @@ def test_submit_validation():
     bad.c.n_beams = 65
     with pytest.raises(lp.LpError):
         srv.open(bad)
+    # int16 samples from 64 stations x 2 pol: 512-byte rows, beyond the
+    # FP16-MFMA tile; accepted at FP32.
+    wide = lp.StreamCfg(np.zeros((64, 3)), range(60, 68), [(0.1, 0.6)], (5.0,),
+                        8192, dtype=lp.LP_CI16, prec=lp.LP_FP16_MFMA)
+    with pytest.raises(lp.LpError, match="256 bytes") as e:
+        srv.open(wide)
+    assert e.value.code == lp.LP_EINVAL
+    wide32 = lp.StreamCfg(np.zeros((64, 3)), range(60, 68), [(0.1, 0.6)],
+                          (5.0,), 8192, dtype=lp.LP_CI16, prec=lp.LP_FP32)
+    srv.close_stream(srv.open(wide32))
     srv.destroy()
 
 
