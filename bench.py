@@ -69,6 +69,10 @@ def main():
                     help="c5: offered load as a fraction of the GPU")
     ap.add_argument("--max-log2-nt", type=int, default=18,
                     help="c5: longest block is 2^this samples per subband")
+    ap.add_argument("--ppf-iters", type=int, default=25,
+                    help="LSMR iterations of the PPF-inversion leg (0: skip)")
+    ap.add_argument("--ppf-steps", type=int, default=3,
+                    help="timed PPF-inversion solves")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for "
                          "calibrating HBM byte counters)")
@@ -171,6 +175,10 @@ def main():
                                              * cfg.n_t * 1024)) <= 1
                     for t in trig) for pl in blk.pulses)
 
+    ppf = None
+    if a.ppf_iters > 0:
+        ppf = ppf_leg(a, ctx, p, cfg, stream)
+
     plain = None
     if a.plain_steps > 0:
         del p
@@ -219,10 +227,90 @@ def main():
         "pulses_found": f"{found}/{len(blk.pulses)}",
         "roofline": roofline,
         "plain_fp32_pipeline": plain,
+        "ppf_inversion": ppf,
         "cpu_baseline": cpu,
     }
     ctx.close()
     print(json.dumps(out))
+
+
+def ppf_bytes_per_iteration(n_sb: int, n_frames: int) -> float:
+    """HBM bytes one LSMR iteration must move per series: H reads v and
+    reads/writes h, hbar, x (FP32, F frames of 1024) and reads/writes u
+    (complex FP32, n_sb x n_frames); H^T reads u and reads/writes v."""
+    F = n_frames - 15
+    return F * 1024 * 4 * (1 + 6 + 2) + n_sb * n_frames * 8 * (2 + 1)
+
+
+def ppf_leg(a, ctx, p, cfg, stream):
+    """PPF inversion (LSMR on H x = y) of the last block's de-dispersed
+    subbands, every (beam, trial) series, timed with HIP events."""
+    import torch
+    from paper_1612_06592_amd import lp
+    ns, nf, S = cfg.n_beams * cfg.n_tec, cfg.n_t, cfg.n_sb
+    F = nf - 15
+    d = p.bufs["d"]
+    x = torch.empty((ns, F * 1024), dtype=torch.float32, device=d.device)
+    wb = lp.nbytes("lp_ppf_work_bytes", S, ns, nf)
+    work = torch.empty(wb, dtype=torch.uint8, device=d.device)
+    an = torch.empty((ns, a.ppf_iters + 1), dtype=torch.float64,
+                     device=d.device)
+    rn = torch.empty(ns, dtype=torch.float64, device=d.device)
+    lp.ppf_invert(ctx, p.band, d, ns, nf, a.ppf_iters, x, work, an, rn,
+                  stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(a.ppf_steps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        lp.ppf_invert(ctx, p.band, d, ns, nf, a.ppf_iters, x, work, an, rn,
+                      stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+    ynorm = torch.linalg.vector_norm(d.reshape(ns, -1).double(), dim=1)
+    rel = (rn / ynorm).cpu().numpy()
+    an_h = an.cpu().numpy()
+    it_bytes = ns * ppf_bytes_per_iteration(S, nf)
+    achieved = it_bytes * a.ppf_iters / (ms * 1e-3) / 1e9
+    out = {"iterations": a.ppf_iters, "series": ns, "frames": nf,
+           "value": round(ns * nf / (ms * 1e-3), 1),
+           "unit": "frames/s per series (25 iterations)" if a.ppf_iters == 25
+           else f"frames/s per series ({a.ppf_iters} iterations)",
+           "ms_per_solve": round(ms, 3),
+           "ms_per_iteration": round(ms / a.ppf_iters, 4),
+           "rtf": round(cfg.block_seconds * 1e3 / ms, 1),
+           "residual_rel": float(np.max(rel)),
+           "atr_reduction": float(np.max(an_h[:, -1] / an_h[:, 0])),
+           "roofline": {"bound": "hbm",
+                        "kernel": "LSMR iteration (ppf_fwd + ppf_adj)",
+                        "achieved": round(achieved, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "algorithmic_bytes_per_iteration": it_bytes}}
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = ppf_cpu_baseline(cfg, d, a.ppf_iters)
+    del x, work
+    torch.cuda.empty_cache()
+    return out
+
+
+def ppf_cpu_baseline(cfg, d, iters: int, frames: int = 1024):
+    """The oracle's LSMR (numpy FP64) on the first `frames` frames of
+    series 0, scaled to the leg's unit (series-frames per second)."""
+    import oracle
+    from oracle import ppf_lsmr
+    y = d[0, :, :frames].cpu().numpy().astype(np.float64)
+    y = y[..., 0] + 1j * y[..., 1]
+    h = oracle.prototype(1024, 16, 9.0)
+    t0 = time.perf_counter()
+    ppf_lsmr.invert(h, 1024, np.asarray(cfg.k), y, iters)
+    dt = time.perf_counter() - t0
+    # numpy's FFT and elementwise operations run on one thread.
+    return {"value": round(frames / dt, 1), "unit": "frames/s per series",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{iters} LSMR iterations on frames 0..{frames - 1} "
+                      f"of series 0", "seconds": round(dt, 2)}
 
 
 def run_cpu_baseline(blk, hops: int):

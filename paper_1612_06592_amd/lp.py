@@ -89,6 +89,15 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is not built; run python -m paper_1612_06592_amd.build")
+    # torch ships its own HIP and HSA runtimes under the same sonames as
+    # the system ones liblp.so links.  Loading torch first makes the dynamic
+    # linker bind liblp.so to those, so the process has one HIP runtime;
+    # loading liblp.so first would map a second pair, after which torch
+    # finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_float
     L.lp_last_error.restype = C.c_char_p

@@ -56,3 +56,22 @@ def test_ctx_create_without_device_reports_ehip():
     h = C.c_void_p()
     rc = lp.lib().lp_ctx_create(0, C.byref(h))
     assert rc == lp.LP_EHIP and not h
+
+
+def test_one_hip_runtime_per_process():
+    """Loading the library maps a single HIP runtime and a single HSA
+    runtime (torch's, when torch is installed), whatever was imported
+    before: two copies in one process leave torch without a device."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1612_06592_amd import lp\n"
+            "lp.lib()\n"
+            "m = open('/proc/self/maps').read().splitlines()\n"
+            "hip = {l.split()[-1] for l in m if 'libamdhip64' in l}\n"
+            "hsa = {l.split()[-1] for l in m if 'libhsa-runtime64' in l}\n"
+            "print(len(hip), len(hsa))\n" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True,
+                         text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["1", "1"], out.stdout
