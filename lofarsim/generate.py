@@ -111,6 +111,38 @@ def hex_beams(az0: float, el0: float, rings: int,
     return np.array(out, dtype=np.float64)
 
 
+def station_groups(enu, n_groups: int, iters: int = 50) -> np.ndarray:
+    """Partition stations into n_groups spatially compact groups (Lloyd's
+    k-means on the horizontal positions, seeded by farthest-point picks from
+    the station nearest the array centre; deterministic).  Returns the group
+    index of every station; every group is non-empty."""
+    xy = np.asarray(enu, dtype=np.float64)[:, :2]
+    n = xy.shape[0]
+    if not 1 <= n_groups <= n:
+        raise ValueError("need 1 <= n_groups <= n_stations")
+    c0 = int(np.argmin(np.sum((xy - xy.mean(0)) ** 2, axis=1)))
+    seeds = [c0]
+    d = np.sum((xy - xy[c0]) ** 2, axis=1)
+    while len(seeds) < n_groups:
+        i = int(np.argmax(d))
+        seeds.append(i)
+        d = np.minimum(d, np.sum((xy - xy[i]) ** 2, axis=1))
+    cent = xy[seeds].copy()
+    lab = np.zeros(n, dtype=np.int32)
+    for _ in range(iters):
+        dist = np.sum((xy[:, None, :] - cent[None]) ** 2, axis=2)
+        new = np.argmin(dist, axis=1).astype(np.int32)
+        for g in range(n_groups):          # keep every group non-empty
+            if not np.any(new == g):
+                far = int(np.argmax(np.min(dist, axis=1)))
+                new[far] = g
+        if np.array_equal(new, lab) and _ > 0:
+            break
+        lab = new
+        cent = np.stack([xy[lab == g].mean(0) for g in range(n_groups)])
+    return lab
+
+
 def kaiser_sinc(M: int, P: int, beta: float = 9.0) -> np.ndarray:
     """Station PPF prototype: numpy's Kaiser window times a sinc with its
     cutoff at half a subband, normalised to unit sum."""

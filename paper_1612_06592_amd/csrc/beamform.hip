@@ -486,7 +486,7 @@ static lp_status launch_bf(const BfPlan *p, const void *x, long x_nt,
       return set_error(LP_EINVAL, "beamformer: %d-byte time rows too long",
                        row_bytes);
     const long tiles = n_t / T;
-    const int tpw = tiles >= 64 ? 8 : tiles >= 8 ? 4 : 1;
+    const int tpw = tiles >= 8 ? 4 : 1;
     dim3 grid((unsigned)((tiles + tpw - 1) / tpw), n_sb);
     size_t shm = (size_t)T * (KS * 16 + 8) * 2;
     auto args = [&](auto kern) {

@@ -38,7 +38,7 @@ constexpr int kPpfThreads = 1024;
 constexpr int kPpfFs = 1090;       // LDS stride of one packed frame (float2)
 constexpr int kPpfWg = 256;        // frames per workgroup
 constexpr int kPpfChunk = 32;      // real frames per chunk
-constexpr int kPpfNormParts = 256; // partial sums of ||y||^2 per series
+constexpr int kPpfNormParts = 2048; // partial sums of ||y||^2 per series
 constexpr int kPpfStateBytes = 128;
 
 enum { kFwdAnalyze = 0, kFwdLsmr = 1, kFwdResid = 2 };

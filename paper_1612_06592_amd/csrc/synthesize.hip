@@ -253,7 +253,7 @@ lp_status syn_launch(lp_ctx *ctx, const SynPlan *p, int n_sb, const void *d,
   // Frames per workgroup: long blocks amortise the 16-frame warm-up; short
   // ones keep enough workgroups to fill the chip.
   int F = 256;
-  while (F > 128 && (long)n_series * (n_t / F) < 1024) F /= 2;
+  while (F > 128 && (long)n_series * (n_t / F) < 256) F /= 2;
   const long n_wg = n_t / F;
   char *cb = static_cast<char *>(cand);
   SynCand *cd = reinterpret_cast<SynCand *>(cb);

@@ -94,17 +94,32 @@ __global__ __launch_bounds__(kT1Threads) void trig_series_kernel(
   const float thr = k_sigma * sigma;
   const float inv_sigma = sigma > 0.0f ? 1.0f / sigma : 0.0f;
 
-  // Pass A.
+  // Pass A (four 64-window groups per wave and step: their loads are in
+  // flight together).
+  constexpr int kU = 4;
   float pk = 0.0f;
-  for (long base = (long)wave * 64; base < n_t; base += kT1Threads) {
-    long m = base + lane;
-    bool valid = m < n_t && m >= first_valid && sigma > 0.0f;
-    float e = m < n_t ? cq[m].emax : 0.0f;
-    if (valid) pk = fmaxf(pk, e / sigma);
-    unsigned long long b = __ballot(valid && e > thr);
-    if (lane == 0) {
-      bits[base / 32] = (unsigned)b;
-      if (base / 32 + 1 < (n_t + 31) / 32) bits[base / 32 + 1] = (unsigned)(b >> 32);
+  for (long base0 = (long)wave * 64; base0 < n_t;
+       base0 += (long)kT1Threads * kU) {
+    float ev[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long m = base0 + (long)u * kT1Threads + lane;
+      ev[u] = m < n_t ? cq[m].emax : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long base = base0 + (long)u * kT1Threads;
+      if (base >= n_t) break;
+      const long m = base + lane;
+      const float e = ev[u];
+      bool valid = m < n_t && m >= first_valid && sigma > 0.0f;
+      if (valid) pk = fmaxf(pk, e / sigma);
+      unsigned long long b = __ballot(valid && e > thr);
+      if (lane == 0) {
+        bits[base / 32] = (unsigned)b;
+        if (base / 32 + 1 < (n_t + 31) / 32)
+          bits[base / 32 + 1] = (unsigned)(b >> 32);
+      }
     }
   }
   for (int off = 32; off >= 1; off >>= 1) pk = fmaxf(pk, __shfl_xor(pk, off));
