@@ -171,6 +171,45 @@ lp_status lp_beamform(lp_ctx *ctx, const lp_array *array, const lp_band *band,
                       int32_t dtype, int64_t n_t, int32_t prec, void *y,
                       void *hip_stream);
 
+/* ---- two-stage beamforming (Sec. 4, network paragraph) ---------------- */
+/* When the station-side cluster cannot ship every station, it forms
+ * preliminary beams from subsets of the stations and the processing cluster
+ * forms the final beams from those.
+ *   groups: group[st] in 0..n_groups-1 for every station (host memory, read
+ *   during the call); every group non-empty; n_groups <= 32.               */
+typedef struct {
+  int32_t n_groups;
+  const int32_t *group;  /* [n_st]                                          */
+} lp_groups;
+
+/* Stage 1 (station side): for group g and preliminary direction p, the
+ * regular beam (lp_beamform's weights) over the group's stations only:
+ *   y1[g * n_prelim + p][s][t] = sum_{st in g, pol} w(st, pol, s, n_p) x.
+ * x, dtype, n_t, prec as for lp_beamform; y1 is cf32
+ * [n_groups * n_prelim][n_sb][n_t] (lp_beam_bytes), n_groups * n_prelim
+ * <= 64.  LP_EINVAL on bad groups or shapes.                               */
+lp_status lp_beamform_groups(lp_ctx *ctx, const lp_array *array,
+                             const lp_groups *groups, const lp_band *band,
+                             const lp_dir *prelim, int32_t n_prelim,
+                             const void *x, int32_t dtype, int64_t n_t,
+                             int32_t prec, void *y1, void *hip_stream);
+
+/* Stage 2 (processing side): final beam b from the preliminary beams of
+ * every group towards the preliminary direction nearest to n_b (p(b):
+ * largest n_p . n_b, lowest p on ties), re-phased by the group's phase
+ * centre r_g (mean station position):
+ *   y[b][s][t] = sum_g exp(-2 pi i frac(f_s r_g . (n_b - n_p(b)) / c))
+ *                y1[g * n_prelim + p(b)][s][t]
+ * (coefficients in FP64, applied in FP32).  y1 as written by
+ * lp_beamform_groups; y is cf32 [n_beams][n_sb][n_t], n_beams <= 64, any
+ * n_t > 0; 8-byte aligned buffers.                                         */
+lp_status lp_beamform_stage2(lp_ctx *ctx, const lp_array *array,
+                             const lp_groups *groups, const lp_band *band,
+                             const lp_dir *prelim, int32_t n_prelim,
+                             const lp_dir *beams, int32_t n_beams,
+                             const void *y1, int64_t n_t, void *y,
+                             void *hip_stream);
+
 /* Per-subband overlap-save de-dispersion at n_tec trial STEC values (paper
  * Sec. 3, dispersion paragraph).
  *   y    : device cf32 [n_beams][n_sb][n_t] (the beamformer output).

@@ -25,14 +25,22 @@ constexpr size_t kLdsMax = 160 * 1024;
 
 // ------------------------------------------------------------- weights
 
+// st_group / beam_group (both NULL for the regular beamformer): a beam of
+// group g weighs only the stations of group g (two-stage beamforming).
 __device__ inline void weight_value(const double *__restrict__ enu,
                                     const double *__restrict__ azel,
                                     const float *__restrict__ gain,
                                     const double *__restrict__ wscale,
                                     const int *__restrict__ kk, double f0,
                                     double df, int n_pol, int s, int inp,
-                                    int b, float &wr, float &wi) {
+                                    int b, const int *__restrict__ st_group,
+                                    const int *__restrict__ beam_group,
+                                    float &wr, float &wi) {
   int st = inp / n_pol;
+  if (st_group && st_group[st] != beam_group[b]) {
+    wr = wi = 0.0f;
+    return;
+  }
   double az = azel[2 * b], el = azel[2 * b + 1];
   double nx = cos(el) * sin(az), ny = cos(el) * cos(az), nz = sin(el);
   double proj = enu[3 * st] * nx + enu[3 * st + 1] * ny + enu[3 * st + 2] * nz;
@@ -51,7 +59,8 @@ __global__ void bf_weights_mfma_kernel(
     const double *__restrict__ enu, const double *__restrict__ azel,
     const float *__restrict__ gain, const double *__restrict__ wscale,
     const int *__restrict__ kk, double f0, double df, int n_pol, int n_in,
-    int n_beams, int n_sb, int KS, int NT, _Float16 *__restrict__ wf) {
+    int n_beams, int n_sb, int KS, int NT, const int *__restrict__ st_group,
+    const int *__restrict__ beam_group, _Float16 *__restrict__ wf) {
   long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   long per_s = (long)NT * KS * 256;
   if (idx >= per_s * n_sb) return;
@@ -67,8 +76,8 @@ __global__ void bf_weights_mfma_kernel(
   float v = 0.0f;
   if (inp < n_in && b < n_beams) {
     float wr, wi;
-    weight_value(enu, azel, gain, wscale, kk, f0, df, n_pol, s, inp, b, wr,
-                 wi);
+    weight_value(enu, azel, gain, wscale, kk, f0, df, n_pol, s, inp, b,
+                 st_group, beam_group, wr, wi);
     v = (xp == 0) ? (op == 0 ? wr : wi) : (op == 0 ? -wi : wr);
   }
   wf[idx] = (_Float16)v;
@@ -79,14 +88,16 @@ __global__ void bf_weights_fp32_kernel(
     const double *__restrict__ enu, const double *__restrict__ azel,
     const float *__restrict__ gain, const double *__restrict__ wscale,
     const int *__restrict__ kk, double f0, double df, int n_pol, int n_in,
-    int n_beams, int n_sb, float2 *__restrict__ w) {
+    int n_beams, int n_sb, const int *__restrict__ st_group,
+    const int *__restrict__ beam_group, float2 *__restrict__ w) {
   long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)n_sb * n_in * n_beams) return;
   int b = (int)(idx % n_beams);
   int inp = (int)((idx / n_beams) % n_in);
   int s = (int)(idx / ((long)n_beams * n_in));
   float wr, wi;
-  weight_value(enu, azel, gain, wscale, kk, f0, df, n_pol, s, inp, b, wr, wi);
+  weight_value(enu, azel, gain, wscale, kk, f0, df, n_pol, s, inp, b,
+               st_group, beam_group, wr, wi);
   w[idx] = make_float2(wr, wi);
 }
 
@@ -371,10 +382,16 @@ static void put(std::vector<uint8_t> &v, const T &x) {
 
 lp_status get_bf_plan(lp_ctx *ctx, const lp_array *a, const lp_band *band,
                       const lp_dir *beams, int n_beams, int prec,
-                      BfPlan **out) {
+                      BfPlan **out, const int *st_group,
+                      const int *beam_group) {
   const int n_in = a->n_st * a->n_pol;
   std::vector<uint8_t> key;
   put(key, prec);
+  put(key, (int)(st_group != nullptr));
+  if (st_group) {
+    for (int i = 0; i < a->n_st; ++i) put(key, st_group[i]);
+    for (int b = 0; b < n_beams; ++b) put(key, beam_group[b]);
+  }
   put(key, a->n_st);
   put(key, a->n_pol);
   for (int i = 0; i < 3 * a->n_st; ++i) put(key, a->enu_m[i]);
@@ -440,6 +457,13 @@ lp_status get_bf_plan(lp_ctx *ctx, const lp_array *a, const lp_band *band,
     LP_HIP(hipMalloc(&dgain.p, n_in * 4));
     LP_HIP(hipMemcpy(dgain.p, a->gain, n_in * 4, hipMemcpyHostToDevice));
   }
+  DevBuf dsg, dbg;
+  if (st_group) {
+    LP_HIP(hipMalloc(&dsg.p, a->n_st * 4));
+    LP_HIP(hipMalloc(&dbg.p, n_beams * 4));
+    LP_HIP(hipMemcpy(dsg.p, st_group, a->n_st * 4, hipMemcpyHostToDevice));
+    LP_HIP(hipMemcpy(dbg.p, beam_group, n_beams * 4, hipMemcpyHostToDevice));
+  }
   double df = band->fs_hz / kM;
   if (prec == LP_FP16_MFMA) {
     long n = (long)band->n_sb * p->NT * p->KS * 256;
@@ -451,7 +475,8 @@ lp_status get_bf_plan(lp_ctx *ctx, const lp_array *a, const lp_band *band,
                        dim3(256), 0, 0, denu.as<double>(), dazel.as<double>(),
                        dgain.as<float>(), dws.as<double>(), dk.as<int>(),
                        band->f0_hz, df, a->n_pol, n_in, n_beams, band->n_sb,
-                       p->KS, p->NT, p->w.as<_Float16>());
+                       p->KS, p->NT, dsg.as<const int>(), dbg.as<const int>(),
+                       p->w.as<_Float16>());
   } else {
     long n = (long)band->n_sb * n_in * n_beams;
     LP_HIP(hipMalloc(&p->w.p, n * 8));
@@ -459,6 +484,7 @@ lp_status get_bf_plan(lp_ctx *ctx, const lp_array *a, const lp_band *band,
                        dim3(256), 0, 0, denu.as<double>(), dazel.as<double>(),
                        dgain.as<float>(), dws.as<double>(), dk.as<int>(),
                        band->f0_hz, df, a->n_pol, n_in, n_beams, band->n_sb,
+                       dsg.as<const int>(), dbg.as<const int>(),
                        p->w.as<float2>());
   }
   LP_HIP(hipGetLastError());

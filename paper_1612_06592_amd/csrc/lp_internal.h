@@ -73,6 +73,16 @@ struct SynPlan {
   DevBuf kbin;    // i16 [n_sb] bin k of each subband position
 };
 
+// Two-stage beamforming: stage-2 coefficients for one (array, grouping,
+// band, preliminary and final directions).
+struct TsPlan {
+  std::vector<uint8_t> key;
+  int G = 0, P = 0, B = 0, S = 0;
+  DevBuf coef;    // float2 [S][B][G]
+  DevBuf order;   // i32 [B] final beams ordered by their preliminary beam
+  DevBuf pstart;  // i32 [P + 1] ranges of `order` per preliminary beam
+};
+
 }  // namespace lp
 
 struct lp_ctx {
@@ -82,6 +92,7 @@ struct lp_ctx {
   std::vector<std::unique_ptr<lp::BfPlan>> bf;
   std::vector<std::unique_ptr<lp::DdPlan>> dd;
   std::vector<std::unique_ptr<lp::SynPlan>> syn;
+  std::vector<std::unique_ptr<lp::TsPlan>> ts;
 };
 
 namespace lp {
@@ -103,7 +114,8 @@ inline const char *bf_shape_error(int n_in, int dtype, int prec) {
 // Plan lookups (create on first use; creation is synchronous).
 lp_status get_bf_plan(lp_ctx *ctx, const lp_array *a, const lp_band *band,
                       const lp_dir *beams, int n_beams, int prec,
-                      BfPlan **out);
+                      BfPlan **out, const int *st_group = nullptr,
+                      const int *beam_group = nullptr);
 lp_status get_dd_plan(lp_ctx *ctx, const lp_band *band, const double *tec,
                       int n_tec, DdPlan **out);
 lp_status get_syn_plan(lp_ctx *ctx, const lp_band *band, SynPlan **out);

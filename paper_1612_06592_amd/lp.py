@@ -48,6 +48,10 @@ class lp_dir(C.Structure):
     _fields_ = [("az_rad", C.c_double), ("el_rad", C.c_double)]
 
 
+class lp_groups(C.Structure):
+    _fields_ = [("n_groups", C.c_int32), ("group", C.POINTER(C.c_int32))]
+
+
 class lp_trig(C.Structure):
     _fields_ = [("sample", C.c_int64), ("beam", C.c_int32),
                 ("tec", C.c_int32), ("snr", C.c_float), ("peak", C.c_float)]
@@ -137,6 +141,16 @@ def lib():
                                       i64, vp, vp, vp, vp, C.c_size_t, vp]
     L.lp_dedisperse_plain.restype = i32
     L.lp_synthesize_plain.restype = i32
+    L.lp_beamform_groups.argtypes = [vp, C.POINTER(lp_array),
+                                     C.POINTER(lp_groups), C.POINTER(lp_band),
+                                     C.POINTER(lp_dir), i32, vp, i32, i64,
+                                     i32, vp, vp]
+    L.lp_beamform_stage2.argtypes = [vp, C.POINTER(lp_array),
+                                     C.POINTER(lp_groups), C.POINTER(lp_band),
+                                     C.POINTER(lp_dir), i32, C.POINTER(lp_dir),
+                                     i32, vp, i64, vp, vp]
+    for name in ("lp_beamform_groups", "lp_beamform_stage2"):
+        getattr(L, name).restype = i32
     L.lp_ppf_analyze.argtypes = [vp, C.POINTER(lp_band), vp, i32, i64, vp, vp]
     L.lp_ppf_adjoint.argtypes = [vp, C.POINTER(lp_band), vp, i32, i64, vp, vp]
     L.lp_ppf_work_bytes.argtypes = [i32, i32, i64]
@@ -178,7 +192,8 @@ def exported_symbols():
             "lp_syn_state_bytes", "lp_cand_bytes", "lp_trigger_work_bytes",
             "lp_beamform", "lp_dedisperse", "lp_synthesize", "lp_trigger",
             "lp_plain_work_bytes", "lp_dedisperse_plain",
-            "lp_synthesize_plain", "lp_ppf_analyze", "lp_ppf_adjoint",
+            "lp_synthesize_plain", "lp_beamform_groups", "lp_beamform_stage2",
+            "lp_ppf_analyze", "lp_ppf_adjoint",
             "lp_ppf_work_bytes", "lp_ppf_invert", "lp_stream_resident_bytes",
             "lp_block_bytes", "lp_server_create", "lp_server_create_sim",
             "lp_stream_open", "lp_stream_submit", "lp_stream_poll",
@@ -306,6 +321,35 @@ def synthesize_plain(ctx: Ctx, band: Band, d, n_series: int, n_t: int,
                                     n_t, frame0, _ptr(hist), _ptr(x_out),
                                     _ptr(cand), _ptr(work), work.numel(),
                                     _stream(stream)))
+
+
+class Groups:
+    """Station grouping for two-stage beamforming (keeps the host array)."""
+
+    def __init__(self, group, n_groups: int | None = None):
+        self.arr = np.ascontiguousarray(group, dtype=np.int32)
+        self.n = int(self.arr.max()) + 1 if n_groups is None else n_groups
+        self.c = lp_groups(self.n, self.arr.ctypes.data_as(
+            C.POINTER(C.c_int32)))
+
+
+def beamform_groups(ctx: Ctx, array: Array, groups: Groups, band: Band,
+                    prelim: Dirs, x, n_t: int, y1, dtype: int = LP_CI8,
+                    prec: int = LP_FP16_MFMA, stream=None):
+    """Stage 1: y1 [G * P][n_sb][n_t] complex (include/lp.h)."""
+    check(lib().lp_beamform_groups(ctx.h, C.byref(array.c), C.byref(groups.c),
+                                   C.byref(band.c), prelim.arr, prelim.n,
+                                   _ptr(x), dtype, n_t, prec, _ptr(y1),
+                                   _stream(stream)))
+
+
+def beamform_stage2(ctx: Ctx, array: Array, groups: Groups, band: Band,
+                    prelim: Dirs, beams: Dirs, y1, n_t: int, y, stream=None):
+    """Stage 2: y [B][n_sb][n_t] complex from y1 (include/lp.h)."""
+    check(lib().lp_beamform_stage2(ctx.h, C.byref(array.c), C.byref(groups.c),
+                                   C.byref(band.c), prelim.arr, prelim.n,
+                                   beams.arr, beams.n, _ptr(y1), n_t, _ptr(y),
+                                   _stream(stream)))
 
 
 def ppf_analyze(ctx: Ctx, band: Band, x, n_series: int, n_frames: int, y,
