@@ -249,7 +249,7 @@ def ppf_leg(a, ctx, p, cfg, stream):
     from paper_1612_06592_amd import lp
     ns, nf, S = cfg.n_beams * cfg.n_tec, cfg.n_t, cfg.n_sb
     F = nf - 15
-    d = p.bufs["d"]
+    d = p.d_view().reshape(ns, S, nf, 2)
     x = torch.empty((ns, F * 1024), dtype=torch.float32, device=d.device)
     wb = lp.nbytes("lp_ppf_work_bytes", S, ns, nf)
     work = torch.empty(wb, dtype=torch.uint8, device=d.device)
