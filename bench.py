@@ -113,28 +113,42 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(a.warmup):
-        p.step(x)
+    # The trigger of block i (one workgroup per series) runs on a second
+    # stream while block i + 1 is beamformed and de-dispersed; synthesis of
+    # block i + 1 waits for it, since it overwrites the candidates.
+    side = torch.cuda.Stream(device=dev)      # default priority
+    stages = ["beamform", "dedisperse", "synthesize", "trigger"]
+
+    def run_steps(n, ev):
+        prev_trig = None
+        for i in range(n):
+            e = ev[i]
+            e[0].record(stream)
+            p.beamform(x)
+            e[1].record(stream)
+            p.dedisperse()
+            e[2].record(stream)
+            if prev_trig is not None:
+                stream.wait_event(prev_trig)
+            p.synthesize()
+            e[3].record(stream)
+            side.wait_event(e[3])
+            p.trigger(stream=side)
+            e[4].record(side)
+            prev_trig = e[4]
+            p.frame0 += cfg.n_t
+
+    def events(n):
+        return [[torch.cuda.Event(enable_timing=True) for _ in range(5)]
+                for _ in range(n)]
+
+    run_steps(a.warmup, events(a.warmup))
     torch.cuda.synchronize()
     print(f"[bench] warmup done ({a.warmup} steps)", file=sys.stderr, flush=True)
-
-    stages = ["beamform", "dedisperse", "synthesize", "trigger"]
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)]
-          for _ in range(a.steps)]
+    ev = events(a.steps)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for i in range(a.steps):
-        e = ev[i]
-        e[0].record(stream)
-        p.beamform(x)
-        e[1].record(stream)
-        p.dedisperse()
-        e[2].record(stream)
-        p.synthesize()
-        e[3].record(stream)
-        p.trigger()
-        e[4].record(stream)
-        p.frame0 += cfg.n_t
+    run_steps(a.steps, ev)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     stage_ms = {s: [] for s in stages}
@@ -178,6 +192,9 @@ def main():
     ppf = None
     if a.ppf_iters > 0:
         ppf = ppf_leg(a, ctx, p, cfg, stream)
+    two = None
+    if cfg.n_beams > 1:
+        two = two_stage_leg(a, ctx, p, blk, x, stream)
 
     plain = None
     if a.plain_steps > 0:
@@ -228,6 +245,7 @@ def main():
         "roofline": roofline,
         "plain_fp32_pipeline": plain,
         "ppf_inversion": ppf,
+        "two_stage_beamforming": two,
         "cpu_baseline": cpu,
     }
     ctx.close()
@@ -244,12 +262,14 @@ def ppf_bytes_per_iteration(n_sb: int, n_frames: int) -> float:
 
 def ppf_leg(a, ctx, p, cfg, stream):
     """PPF inversion (LSMR on H x = y) of the last block's de-dispersed
-    subbands, every (beam, trial) series, timed with HIP events."""
+    subbands (up to 8 (beam, trial) series), timed with HIP events."""
     import torch
     from paper_1612_06592_amd import lp
-    ns, nf, S = cfg.n_beams * cfg.n_tec, cfg.n_t, cfg.n_sb
+    # At most 8 series (the first beams/trials of the block) keep the
+    # workspace bounded on the many-series workloads.
+    ns, nf, S = min(8, cfg.n_beams * cfg.n_tec), cfg.n_t, cfg.n_sb
     F = nf - 15
-    d = p.d_view().reshape(ns, S, nf, 2)
+    d = p.d_view().reshape(-1, S, nf, 2)[:ns]
     x = torch.empty((ns, F * 1024), dtype=torch.float32, device=d.device)
     wb = lp.nbytes("lp_ppf_work_bytes", S, ns, nf)
     work = torch.empty(wb, dtype=torch.uint8, device=d.device)
@@ -291,6 +311,61 @@ def ppf_leg(a, ctx, p, cfg, stream):
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = ppf_cpu_baseline(cfg, d, a.ppf_iters)
     del x, work
+    torch.cuda.empty_cache()
+    return out
+
+
+def two_stage_leg(a, ctx, p, blk, x, stream, n_groups: int = 8,
+                  steps: int = 5):
+    """Two-stage beamforming of the block (8 compact station groups, 7
+    preliminary beams: the centre beam and a ring at 0.2 deg), timed with
+    HIP events beside the single-stage beamformer on the same block."""
+    import torch
+
+    import lofarsim
+    from paper_1612_06592_amd import lp
+    cfg = blk.cfg
+    group = lofarsim.station_groups(blk.enu, n_groups)
+    prelim = lofarsim.hex_beams(blk.az_el[0][0], blk.az_el[0][1], 1,
+                                spacing_deg=0.2)
+    G, P, S, n_t = n_groups, len(prelim), cfg.n_sb, cfg.n_t
+    grp, pre = lp.Groups(group, G), lp.Dirs(prelim)
+    y1 = torch.empty((G * P, S, n_t, 2), dtype=torch.float32, device=x.device)
+    dt = lp.LP_CI8 if cfg.dtype == "ci8" else lp.LP_CI16
+
+    def s1():
+        lp.beamform_groups(ctx, p.array, grp, p.band, pre, x, n_t, y1,
+                           dtype=dt, prec=p.prec, stream=stream)
+
+    def s2():
+        lp.beamform_stage2(ctx, p.array, grp, p.band, pre, p.dirs, y1, n_t,
+                           p.y_view(), stream=stream)
+
+    def single():
+        p.beamform(x, stream)
+
+    out = {}
+    for name, fn in (("stage1_ms", s1), ("stage2_ms", s2),
+                     ("single_stage_ms", single)):
+        fn()
+        ev = [(torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for e0, e1 in ev:
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = round(float(np.mean([e0.elapsed_time(e1)
+                                         for e0, e1 in ev])), 4)
+    bytes2 = (G * P + cfg.n_beams) * S * n_t * 8
+    gbs = bytes2 / (out["stage2_ms"] * 1e-3) / 1e9
+    out.update({"groups": G, "preliminary_beams": P,
+                "final_beams": cfg.n_beams,
+                "stage2_roofline": {"bound": "hbm", "achieved": round(gbs, 1),
+                                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                    "algorithmic_bytes_per_launch": bytes2}})
+    del y1
     torch.cuda.empty_cache()
     return out
 
