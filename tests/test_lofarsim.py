@@ -57,3 +57,21 @@ def test_serving_stream_shapes():
     for s in ss:
         assert 24 <= s["n_st"] <= 48 and s["n_beams"] in (7, 19, 37, 61)
         assert min(s["k"]) >= 1 and max(s["k"]) <= 511
+
+
+def test_station_groups_partition():
+    """Every station in exactly one of n non-empty groups, deterministic,
+    and groups are compact: each station is nearer its own group centre
+    than any other centre (the k-means fixed point)."""
+    import numpy as np
+    rng = np.random.default_rng(5)
+    enu = lofarsim.stations_in_disk(rng, 48, 2000.0)
+    a = lofarsim.station_groups(enu, 8)
+    b = lofarsim.station_groups(enu.copy(), 8)
+    assert np.array_equal(a, b)
+    assert a.shape == (48,) and set(a.tolist()) == set(range(8))
+    cent = np.stack([enu[a == g, :2].mean(0) for g in range(8)])
+    d = np.sum((enu[:, None, :2] - cent[None]) ** 2, axis=2)
+    assert np.array_equal(np.argmin(d, axis=1), a)
+    one = lofarsim.station_groups(enu, 48)
+    assert sorted(one.tolist()) == list(range(48))

@@ -166,3 +166,49 @@ def test_zero_input():
     h, rng, k = _setup(M, P, F, [3, 4, 5])
     x, an = pl.invert(h, M, k, np.zeros((3, F + P - 1), complex), 25)
     assert x.shape == (F * M,) and not np.any(x) and an == [0.0]
+
+
+def _band_noise(rng, N, M, k):
+    X = np.fft.rfft(rng.standard_normal(N))
+    f = np.arange(X.size) / N
+    X[(f < (k[0] - 0.5) / M) | (f > (k[-1] + 0.5) / M)] = 0
+    return np.fft.irfft(X, N)
+
+
+def test_fidelity_gain_over_one_shot_synthesis():
+    """The gain LSMR buys over the one-shot synthesis filterbank (the trigger
+    path's inversion): noise filling the recorded band, including the
+    subband crossovers, is reconstructed at ~35 dB after 25 iterations
+    against ~14 dB; a tone at a subband edge keeps its amplitude (synthesis:
+    -6 dB, the scalloping of two crossing channels)."""
+    M, P, F = 1024, 16, 48
+    h, rng, k = _setup(M, P, F, range(100, 132), 0)
+    N = F * M
+    lag = 15 * M + 1           # synthesis delay in this frame alignment
+    a, b = 16 * M, N - 16 * M
+
+    def synth(y):
+        z = oracle.synthesize(h, k, y[None], np.zeros((1, 15, len(k)), complex))
+        seg = 2 * z[0].real[lag:lag + N]
+        return np.concatenate([seg, np.zeros(N - seg.size)])
+
+    def snr(v, x):
+        return 10 * np.log10(np.sum(x[a:b] ** 2) / np.sum((v - x)[a:b] ** 2))
+
+    x = _band_noise(rng, N, M, k)
+    y = pl.analysis(h, M, k, x)
+    s_syn = snr(synth(y), x)
+    s_lsmr = snr(pl.invert(h, M, k, y, 25)[0], x)
+    assert 10 < s_syn < 20 and s_lsmr > 30, (s_syn, s_lsmr)
+    n = np.arange(N)
+    for d, syn_db in ((0.0, 0.0), (0.25, 0.0), (0.5, -6.02)):
+        nu = (115 + d) / M
+        xt = np.cos(2 * np.pi * nu * n + 0.3)
+        yt = pl.analysis(h, M, k, xt)
+        ref = np.exp(2j * np.pi * nu * n[a:b])
+
+        def amp_db(v):
+            return 20 * np.log10(abs(np.dot(v[a:b], np.conj(ref))) / ((b - a) / 2))
+
+        assert abs(amp_db(synth(yt)) - syn_db) < 0.05
+        assert abs(amp_db(pl.invert(h, M, k, yt, 25)[0])) < 0.01
