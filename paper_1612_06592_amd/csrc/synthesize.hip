@@ -23,6 +23,10 @@
 namespace lp {
 
 constexpr int kSynThreads = 1024;
+
+// Twiddle-table slot of entry n: one pad slot every 8 entries spreads the
+// strided pass-1 reads of a wave over distinct banks.
+__device__ __forceinline__ int twp(int n) { return n + (n >> 3); }
 constexpr int kSynFs = 1089;  // LDS frame stride (>= pad16(1023)+1, odd)
 
 struct SynCand {
@@ -37,7 +41,7 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     SynCand *__restrict__ cand, float *__restrict__ psum, int n_sb, long n_t,
     long frame0, long warm, int F, long cand_nt, long cand_t0) {
   __shared__ float2 lds[16 * kSynFs];
-  __shared__ float2 tw1k[1024];   // exp(+2 pi i n / 1024)
+  __shared__ float2 tw1k[1024 + 128];   // exp(+2 pi i n / 1024) at twp(n)
   __shared__ float red_s[16];
 
   const int series = blockIdx.y;
@@ -57,7 +61,7 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
   for (int t = 0; t < 16; ++t) win[t] = make_float2(0.f, 0.f);
   {
     float2 w = tw[4 * tid];
-    tw1k[tid] = make_float2(w.x, -w.y);
+    tw1k[twp(tid)] = make_float2(w.x, -w.y);
   }
   // (the first barrier in the chunk loop orders these writes before use)
 
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
       {
         const int jm = (jo & 15) * 4;  // angle 2 pi (j mod 16) r / 256
 #pragma unroll
-        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw1k[(jm * r) & 1023]);
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw1k[twp((jm * r) & 1023)]);
       }
       dft16<true>(v);
       __syncthreads();
@@ -132,9 +136,9 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
         int jj = jo + 64 * q, jt = jj;
         float2 a0 = fr[pad16(jj)], a1 = fr[pad16(jj + 256)],
                a2 = fr[pad16(jj + 512)], a3 = fr[pad16(jj + 768)];
-        a1 = cmul(a1, tw1k[jt]);
-        a2 = cmul(a2, tw1k[2 * jt]);
-        a3 = cmul(a3, tw1k[(3 * jt) & 1023]);
+        a1 = cmul(a1, tw1k[twp(jt)]);
+        a2 = cmul(a2, tw1k[twp(2 * jt)]);
+        a3 = cmul(a3, tw1k[twp((3 * jt) & 1023)]);
         dft4<true>(a0, a1, a2, a3);
         fr[pad16(jj)] = a0;
         fr[pad16(jj + 256)] = a1;
