@@ -88,6 +88,8 @@ def main():
                     help="LSMR iterations of the PPF-inversion leg (0: skip)")
     ap.add_argument("--ppf-steps", type=int, default=3,
                     help="timed PPF-inversion solves")
+    ap.add_argument("--no-sim", action="store_true",
+                    help="skip the station-simulator leg")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for "
                          "calibrating HBM byte counters)")
@@ -222,6 +224,9 @@ def main():
     two = None
     if cfg.n_beams > 1:
         two = two_stage_leg(a, ctx, p, blk, x, stream)
+    sim = None
+    if not a.no_sim:
+        sim = station_sim_leg(a, ctx, cfg, blk, stream)
 
     plain = None
     if a.plain_steps > 0:
@@ -273,6 +278,7 @@ def main():
         "plain_fp32_pipeline": plain,
         "ppf_inversion": ppf,
         "two_stage_beamforming": two,
+        "station_simulator": sim,
         "cpu_baseline": cpu,
     }
     ctx.close()
@@ -394,6 +400,69 @@ def two_stage_leg(a, ctx, p, blk, x, stream, n_groups: int = 8,
                                     "algorithmic_bytes_per_launch": bytes2}})
     del y1
     torch.cuda.empty_cache()
+    return out
+
+
+def station_sim_leg(a, ctx, cfg, blk, stream, steps: int = 3):
+    """The station simulator for one block of the workload's shape: every
+    input's 5 ns ADC stream (Philox noise, 16 words) with 15 frames of
+    history, then the station filterbank into the beamformer's input
+    layout; HIP events around each stage."""
+    import torch
+    from paper_1612_06592_amd import lp
+    n_in, S, nf = cfg.n_in, cfg.n_sb, cfg.n_t
+    n_samp = (nf + 15) * 1024
+    band = lp.Band(blk.k)
+    adc = torch.empty((n_in, n_samp), dtype=torch.int16, device="cuda:0")
+    x = torch.empty((S, nf, n_in, 2),
+                    dtype=torch.int8 if cfg.dtype == "ci8" else torch.int16,
+                    device="cuda:0")
+    work = torch.empty(lp.nbytes("lp_station_work_bytes", n_in, S, nf),
+                       dtype=torch.uint8, device="cuda:0")
+    dt = lp.LP_CI8 if cfg.dtype == "ci8" else lp.LP_CI16
+    # Subband sigma 8 from ADC sigma sqrt(128) (16 noise words).
+    import lofarsim
+    hp = lofarsim.kaiser_sinc(1024, 16)
+    scale = 8.0 / (np.sqrt(128.0) * np.sqrt(np.sum(hp * hp) / 2))
+
+    def run(e):
+        e[0].record(stream)
+        lp.sim_adc(ctx, 1612, n_in, 16, 12, 1, n_samp, adc, stream=stream)
+        e[1].record(stream)
+        lp.station_ppf(ctx, band, adc, n_in, nf, scale, x, work, dt,
+                       stream=stream)
+        e[2].record(stream)
+
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)]
+          for _ in range(steps + 1)]
+    for e in ev:
+        run(e)
+    torch.cuda.synchronize()
+    t_adc = float(np.mean([e[0].elapsed_time(e[1]) for e in ev[1:]]))
+    t_ppf = float(np.mean([e[1].elapsed_time(e[2]) for e in ev[1:]]))
+    total = t_adc + t_ppf
+    samples = n_in * n_samp
+    out = {"inputs": n_in, "adc_samples": samples, "subbands": S,
+           "frames": nf, "adc_ms": round(t_adc, 3),
+           "station_ppf_ms": round(t_ppf, 3),
+           "value": round(samples / (total * 1e-3) / 1e9, 2),
+           "unit": "G ADC samples/s (noise + station filterbank)",
+           "rtf": round(cfg.block_seconds * 1e3 / total, 1)}
+    del adc, x, work
+    torch.cuda.empty_cache()
+    if not a.no_cpu_baseline:
+        import oracle
+        from oracle import station_sim
+        h = oracle.prototype(1024, 16, 9.0)
+        t0 = time.perf_counter()
+        codes = station_sim.adc(1612, 1, 16, 12, 1, (64 + 15) * 1024)
+        station_sim.station_ppf(h, 1024, np.asarray(blk.k), codes, scale, 8)
+        dt_cpu = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(64 * 1024 / dt_cpu / 1e9, 6),
+            "unit": "G ADC samples/s", "cores": 1, "kind": "oracle",
+            "sample": "1 input x 64 frames (numpy)",
+            "seconds": round(dt_cpu, 2)}
     return out
 
 

@@ -312,6 +312,42 @@ lp_status lp_ppf_invert(lp_ctx *ctx, const lp_band *band, const void *y,
                         float *x, double *anorm, double *rnorm, void *work,
                         size_t work_bytes, void *hip_stream);
 
+/* ---- station simulator (Sec. 2: 5 ns sampling and the station PPF;
+ *      Sec. 5: the simulation chain's PPF module) ----------------------- */
+typedef struct {
+  uint64_t seed;        /* Philox4x32-10 key: (seed mod 2^32, seed div 2^32) */
+  int32_t n_in;         /* inputs (stations x polarisations)                */
+  int32_t noise_words;  /* R in 0..256: noise variance 8 R ADC units^2      */
+  int32_t adc_bits;     /* codes saturate to [-2^(b-1), 2^(b-1) - 1], 2..16 */
+} lp_sim_cfg;
+
+/* ADC codes of every input for absolute samples n0 .. n0 + n_samp - 1:
+ *   noise_i[n] = sum_{r < R} (popcount(w_r) - 16)
+ * with w_r the words of Philox4x32-10 (Salmon et al. 2011) under the key and
+ * the counter (n mod 2^32, n div 2^32, i, r div 4) (word r mod 4), so any
+ * split of the sample range gives the same codes; plus, if pulse is not
+ * NULL, rint (half to even) of pulse[i][n - pulse_n0] for n in [pulse_n0,
+ * pulse_n0 + pulse_len); then saturated.  pulse: device float
+ * [n_in][pulse_len]; adc: device int16 [n_in][n_samp].                      */
+lp_status lp_sim_adc(lp_ctx *ctx, const lp_sim_cfg *cfg, int64_t n0,
+                     int64_t n_samp, const float *pulse, int64_t pulse_n0,
+                     int64_t pulse_len, int16_t *adc, void *hip_stream);
+
+/* The station polyphase filterbank (prototype h of band->kaiser_beta,
+ * M = 1024, 16 taps) of every input's ADC stream, for the subbands band->k:
+ *   y_s[m] = sum_{l < 16384} h[l] exp(+2 pi i k_s l / 1024)
+ *            adc[1024 (m + 16) - 1 - l]
+ * for output frames m = 0 .. n_frames - 1 (adc holds 15 frames of history
+ * before them: [n_in][(n_frames + 15) * 1024] int16), times scale, rounded
+ * half to even and saturated to the int8 or int16 range (dtype LP_CI8 or
+ * LP_CI16), written as the beamformer's input x [n_sb][n_frames][n_in]
+ * complex.  n_in <= 128.  work: device, >= lp_station_work_bytes().        */
+size_t lp_station_work_bytes(int32_t n_in, int32_t n_sb, int64_t n_frames);
+lp_status lp_station_ppf(lp_ctx *ctx, const lp_band *band, const int16_t *adc,
+                         int32_t n_in, int64_t n_frames, float scale,
+                         int32_t dtype, void *x, void *work,
+                         size_t work_bytes, void *hip_stream);
+
 /* ---- serving: concurrent observation streams ------------------------- */
 /* A persistent request loop (one host thread) runs the four stages for many
  * observation streams.  Each open stream keeps its overlap-save tail and

@@ -14,5 +14,5 @@ from ``numpy.random.SeedSequence``.
 """
 from .configs import CONFIGS, Workload, get_config, serving_streams  # noqa
 from .generate import (Block, generate, hex_beams, kaiser_sinc,  # noqa
-                       station_groups, station_ppf, stations_in_disk,
-                       moon_direction)
+                       pulse_waveforms, station_groups, station_ppf,
+                       stations_in_disk, moon_direction)

@@ -171,10 +171,14 @@ def station_ppf(x: np.ndarray, w0: int, h: np.ndarray, M: int,
     return out
 
 
-def _pulse_subbands(cfg: Workload, enu, src_dir, n0: int, amp: float,
-                    tec: float, h: np.ndarray):
-    """Per-station subband contribution of one pulse: (m_first, y) with
-    y[st][s][i] complex for frames m_first + i."""
+def pulse_waveforms(cfg: Workload, enu, src_dir, n0: int, amp: float,
+                    tec: float):
+    """5 ns waveform of one pulse at every station: (w0, xs) with xs[st][j]
+    the real ADC-domain signal at absolute sample w0 + j (PULSE_WINDOW
+    samples).  An impulse at ADC sample n0 at the array origin, arriving
+    (r . n) / c earlier at station r, dispersed by the ionosphere
+    (exp(+2 pi i kappa T / f_RF)), band-limited to the selected subbands;
+    baseband frequency f_b maps to f_RF = f0 + f_b."""
     M, fs, f0 = cfg.M, cfg.fs, cfg.f0
     Nw = PULSE_WINDOW
     frame = n0 // M
@@ -188,17 +192,32 @@ def _pulse_subbands(cfg: Workload, enu, src_dir, n0: int, amp: float,
     base = amp * np.exp(-2j * np.pi * nb * (n0 - w0) / Nw)
     iono = np.exp(2j * np.pi * (K_ION * tec * TECU / C_LIGHT) / f_rf)
     nvec = _unit(*src_dir)
+    xs = np.empty((enu.shape[0], Nw))
+    for st in range(enu.shape[0]):
+        tau = -(enu[st] @ nvec) / C_LIGHT
+        spec = np.where(band, base * iono * np.exp(-2j * np.pi * f_rf * tau),
+                        0.0)
+        xs[st] = np.fft.irfft(spec, n=Nw)
+    return w0, xs
+
+
+def _pulse_subbands(cfg: Workload, enu, src_dir, n0: int, amp: float,
+                    tec: float, h: np.ndarray):
+    """Per-station subband contribution of one pulse: (m_first, y) with
+    y[st][s][i] complex for frames m_first + i."""
+    M = cfg.M
+    Nw = PULSE_WINDOW
+    w0, xs = pulse_waveforms(cfg, enu, src_dir, n0, amp, tec)
     m_first = w0 // M
     n_frames = Nw // M + h.size // M
     ks = np.asarray(cfg.k)
     y = np.empty((enu.shape[0], ks.size, n_frames), dtype=np.complex128)
     for st in range(enu.shape[0]):
-        tau = -(enu[st] @ nvec) / C_LIGHT
-        spec = np.where(band, base * iono * np.exp(-2j * np.pi * f_rf * tau),
-                        0.0)
-        xs = np.fft.irfft(spec, n=Nw)
-        y[st] = station_ppf(xs, w0, h, M, m_first, n_frames)[ks]
-    n_band = int(band.sum())
+        y[st] = station_ppf(xs[st], w0, h, M, m_first, n_frames)[ks]
+    fb = np.arange(Nw // 2 + 1) * cfg.fs / Nw
+    df = cfg.fs / M
+    n_band = int(((fb >= (min(cfg.k) - 0.5) * df) &
+                  (fb <= (max(cfg.k) + 0.5) * df)).sum())
     return m_first, y, n_band
 
 

@@ -41,7 +41,7 @@ constexpr int kPpfChunk = 32;      // real frames per chunk
 constexpr int kPpfNormParts = 2048; // partial sums of ||y||^2 per series
 constexpr int kPpfStateBytes = 128;
 
-enum { kFwdAnalyze = 0, kFwdLsmr = 1, kFwdResid = 2 };
+enum { kFwdAnalyze = 0, kFwdLsmr = 1, kFwdResid = 2, kFwdStation = 3 };
 enum { kAdjPlain = 0, kAdjLsmr = 1 };
 
 // LSMR state of one series (device memory, written by the scalar kernels).
@@ -121,14 +121,19 @@ __device__ __forceinline__ void wg_sum_store(float acc, float *red,
 
 // H (kFwdAnalyze: yout = H x), one LSMR half-step (kFwdLsmr: q = H (p
 // p_scale) - q_scale q in place, plus the pending update of hbar, x, h
-// from p), or the residual norm (kFwdResid: partials of |y - H x|^2).
+// from p), the residual norm (kFwdResid: partials of |y - H x|^2), or the
+// station filterbank (kFwdStation: int16 ADC input; the valid frames
+// m' >= 15 of H, times oscale, rounded half to even and saturated to
+// [-olim, olim - 1], go to sout [series][n_sb][nf - 30] as int16 pairs).
+// xin is float, or int16 in station mode.
 template <int MODE>
 __global__ __launch_bounds__(kPpfThreads) void ppf_fwd_kernel(
-    const float *__restrict__ xin, const float2 *yin, float2 *yout,
+    const void *__restrict__ xin_, const float2 *yin, float2 *yout,
     float *__restrict__ hv, float *__restrict__ hbar, float *__restrict__ xv,
     const LsmrState *__restrict__ st, float *__restrict__ part,
     const short *__restrict__ kbin, const float *__restrict__ taps,
-    const float2 *__restrict__ tw, int n_sb, long nf, int n_part) {
+    const float2 *__restrict__ tw, int n_sb, long nf, int n_part,
+    float oscale = 1.f, int olim = 0, short2 *__restrict__ sout = nullptr) {
   __shared__ float2 lds[16 * kPpfFs];
   __shared__ float2 tw1k[1024];
   __shared__ float red[16];
@@ -139,7 +144,12 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_fwd_kernel(
   const long N = F * kM;
   const int tid = threadIdx.x;
   const int f = tid & 15, j = tid >> 4;  // transform layout
-  const float *xs = xin + (long)series * N;
+  const float *xs = static_cast<const float *>(xin_) + (long)series * N;
+  const short *xq = static_cast<const short *>(xin_) + (long)series * N;
+  auto ld = [&](long idx) -> float {
+    return MODE == kFwdStation ? (float)xq[idx] : xs[idx];
+  };
+  const long nout = nf - 2 * (kTaps - 1);  // station mode: valid frames
   const long vbase = (long)series * N;
   const float2 *yi = yin + (long)series * n_sb * nf;
   float2 *yo = yout + (long)series * n_sb * nf;
@@ -167,7 +177,7 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_fwd_kernel(
 #pragma unroll
   for (int i = 1; i < 16; ++i) {
     const long m = m0 - 16 + i;
-    ring[i] = (m >= 0 && m < F) ? xs[m * kM + (kM - 1 - tid)] * sc : 0.f;
+    ring[i] = (m >= 0 && m < F) ? ld(m * kM + (kM - 1 - tid)) * sc : 0.f;
   }
   float acc = 0.f;
   for (int c = 0; c < kPpfWg / kPpfChunk; ++c) {
@@ -186,7 +196,7 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_fwd_kernel(
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const long m = mc + 8 * g8 + i;
-        pv[i] = (m < F) ? xs[m * kM + (kM - 1 - ro)] : 0.f;
+        pv[i] = (m < F) ? ld(m * kM + (kM - 1 - ro)) : 0.f;
       }
       if (MODE == kFwdLsmr) {
         // Pending update (hbar_k, x_k, h_{k+1}) on the unknowns this
@@ -256,6 +266,17 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_fwd_kernel(
         if (m + e < nf) {
           if (MODE == kFwdAnalyze) {
             yo[o + e] = val[e];
+          } else if (MODE == kFwdStation) {
+            const long mo = m + e - (kTaps - 1);
+            if (mo >= 0 && mo < nout) {
+              const float lim = (float)olim;
+              const float re = fminf(fmaxf(rintf(val[e].x * oscale), -lim),
+                                     lim - 1.f);
+              const float im = fminf(fmaxf(rintf(val[e].y * oscale), -lim),
+                                     lim - 1.f);
+              sout[((long)series * n_sb + s) * nout + mo] =
+                  make_short2((short)re, (short)im);
+            }
           } else if (MODE == kFwdLsmr) {
             const float2 q0 = yi[o + e];
             const float2 qn = make_float2(val[e].x - qs * q0.x,
@@ -271,7 +292,7 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_fwd_kernel(
       }
     }
   }
-  if (MODE != kFwdAnalyze)
+  if (MODE == kFwdLsmr || MODE == kFwdResid)
     wg_sum_store(acc, red, part + (long)series * n_part + blockIdx.x);
 }
 
@@ -553,6 +574,36 @@ __global__ void ppf_rnorm_kernel(const float *__restrict__ part, int n_part,
   if (threadIdx.x == 0) out[series] = sqrt(r2);
 }
 
+// Station subbands from the staging buffer [n_in][P] (int16 pairs, P =
+// n_sb * n_frames positions) to the beamformer's layout [P][n_in] (int8 or
+// int16 pairs): 64 positions of every input per workgroup through LDS.
+__global__ __launch_bounds__(256) void station_transpose_kernel(
+    const short2 *__restrict__ st, long P, int n_in, int ci8,
+    void *__restrict__ x) {
+  __shared__ short2 tile[64][129];
+  const long p0 = (long)blockIdx.x * 64;
+  for (int idx = threadIdx.x; idx < 64 * n_in; idx += 256) {
+    const int i = idx / 64, pp = idx % 64;
+    tile[pp][i] = (p0 + pp < P) ? st[(long)i * P + p0 + pp]
+                                : make_short2(0, 0);
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 64 * n_in; idx += 256) {
+    const int pp = idx / n_in, i = idx % n_in;
+    if (p0 + pp >= P) continue;
+    const short2 v = tile[pp][i];
+    const long o = (p0 + pp) * n_in + i;
+    if (ci8) {
+      char2 c;
+      c.x = (signed char)v.x;
+      c.y = (signed char)v.y;
+      static_cast<char2 *>(x)[o] = c;
+    } else {
+      static_cast<short2 *>(x)[o] = v;
+    }
+  }
+}
+
 // ------------------------------------------------------------- host side
 
 struct PpfLayout {
@@ -735,6 +786,58 @@ extern "C" lp_status lp_ppf_invert(lp_ctx *ctx, const lp_band *band,
     hipLaunchKernelGGL(ppf_rnorm_kernel, dim3(n_series), dim3(64), 0, hs,
                        part, L.n_fwd, rnorm);
   }
+  LP_HIP(hipGetLastError());
+  return LP_OK;
+}
+
+extern "C" size_t lp_station_work_bytes(int32_t n_in, int32_t n_sb,
+                                        int64_t n_frames) {
+  if (n_in <= 0 || n_sb <= 0 || n_frames <= 0) return 0;
+  return (size_t)n_in * n_sb * n_frames * 4;
+}
+
+extern "C" lp_status lp_station_ppf(lp_ctx *ctx, const lp_band *band,
+                                    const int16_t *adc, int32_t n_in,
+                                    int64_t n_frames, float scale,
+                                    int32_t dtype, void *x, void *work,
+                                    size_t work_bytes, void *hip_stream) {
+  if (!ctx || !adc || !x || !work)
+    return set_error(LP_EINVAL, "lp_station_ppf: NULL argument");
+  lp_status rc = check_band(band);
+  if (rc) return rc;
+  if (n_in < 1 || n_in > 128)
+    return set_error(LP_EINVAL, "lp_station_ppf: n_in %d not in 1..128", n_in);
+  if (n_frames < 1 || n_frames > (1L << 24))
+    return set_error(LP_EINVAL, "lp_station_ppf: n_frames %lld",
+                     (long long)n_frames);
+  if (!(scale > 0.f) || !std::isfinite(scale))
+    return set_error(LP_EINVAL, "lp_station_ppf: scale must be positive");
+  if (dtype != LP_CI8 && dtype != LP_CI16)
+    return set_error(LP_EINVAL, "lp_station_ppf: dtype %d", dtype);
+  if (work_bytes < lp_station_work_bytes(n_in, band->n_sb, n_frames))
+    return set_error(LP_EINVAL, "lp_station_ppf: work %zu bytes too small",
+                     work_bytes);
+  if (!aligned(adc, 2) || !aligned(x, dtype == LP_CI8 ? 2 : 4) ||
+      !aligned(work, 4))
+    return set_error(LP_EINVAL, "lp_station_ppf: misaligned buffer");
+  if ((rc = set_device(ctx))) return rc;
+  SynPlan *p = nullptr;
+  if ((rc = get_syn_plan(ctx, band, &p))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const long nf = n_frames + 2 * (kTaps - 1);   // frames of H's output
+  const int n_fwd = (int)((nf + kPpfWg - 1) / kPpfWg);
+  short2 *stage = static_cast<short2 *>(work);
+  hipLaunchKernelGGL(ppf_fwd_kernel<kFwdStation>, dim3(n_fwd, n_in),
+                     dim3(kPpfThreads), 0, st, adc, (const float2 *)nullptr,
+                     (float2 *)nullptr, nullptr, nullptr, nullptr, nullptr,
+                     nullptr, p->kbin.as<const short>(),
+                     p->taps.as<const float>(), ctx->tw4096.as<const float2>(),
+                     band->n_sb, nf, 0, scale, dtype == LP_CI8 ? 128 : 32768,
+                     stage);
+  const long P = (long)band->n_sb * n_frames;
+  hipLaunchKernelGGL(station_transpose_kernel, dim3((unsigned)((P + 63) / 64)),
+                     dim3(256), 0, st, stage, P, (int)n_in,
+                     dtype == LP_CI8 ? 1 : 0, x);
   LP_HIP(hipGetLastError());
   return LP_OK;
 }

@@ -52,6 +52,11 @@ class lp_groups(C.Structure):
     _fields_ = [("n_groups", C.c_int32), ("group", C.POINTER(C.c_int32))]
 
 
+class lp_sim_cfg(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("n_in", C.c_int32),
+                ("noise_words", C.c_int32), ("adc_bits", C.c_int32)]
+
+
 class lp_trig(C.Structure):
     _fields_ = [("sample", C.c_int64), ("beam", C.c_int32),
                 ("tec", C.c_int32), ("snr", C.c_float), ("peak", C.c_float)]
@@ -151,6 +156,14 @@ def lib():
                                      i32, vp, i64, vp, vp]
     for name in ("lp_beamform_groups", "lp_beamform_stage2"):
         getattr(L, name).restype = i32
+    L.lp_sim_adc.argtypes = [vp, C.POINTER(lp_sim_cfg), i64, i64, vp, i64,
+                             i64, vp, vp]
+    L.lp_sim_adc.restype = i32
+    L.lp_station_work_bytes.argtypes = [i32, i32, i64]
+    L.lp_station_work_bytes.restype = C.c_size_t
+    L.lp_station_ppf.argtypes = [vp, C.POINTER(lp_band), vp, i32, i64, f32,
+                                 i32, vp, vp, C.c_size_t, vp]
+    L.lp_station_ppf.restype = i32
     L.lp_ppf_analyze.argtypes = [vp, C.POINTER(lp_band), vp, i32, i64, vp, vp]
     L.lp_ppf_adjoint.argtypes = [vp, C.POINTER(lp_band), vp, i32, i64, vp, vp]
     L.lp_ppf_work_bytes.argtypes = [i32, i32, i64]
@@ -194,7 +207,9 @@ def exported_symbols():
             "lp_plain_work_bytes", "lp_dedisperse_plain",
             "lp_synthesize_plain", "lp_beamform_groups", "lp_beamform_stage2",
             "lp_ppf_analyze", "lp_ppf_adjoint",
-            "lp_ppf_work_bytes", "lp_ppf_invert", "lp_stream_resident_bytes",
+            "lp_ppf_work_bytes", "lp_ppf_invert", "lp_sim_adc",
+            "lp_station_work_bytes", "lp_station_ppf",
+            "lp_stream_resident_bytes",
             "lp_block_bytes", "lp_server_create", "lp_server_create_sim",
             "lp_stream_open", "lp_stream_submit", "lp_stream_poll",
             "lp_stream_close", "lp_server_destroy", "lp_server_stats"]
@@ -350,6 +365,27 @@ def beamform_stage2(ctx: Ctx, array: Array, groups: Groups, band: Band,
                                    C.byref(band.c), prelim.arr, prelim.n,
                                    beams.arr, beams.n, _ptr(y1), n_t, _ptr(y),
                                    _stream(stream)))
+
+
+def sim_adc(ctx: Ctx, seed: int, n_in: int, noise_words: int, adc_bits: int,
+            n0: int, n_samp: int, adc, pulse=None, pulse_n0: int = 0,
+            stream=None):
+    """ADC codes int16 [n_in][n_samp] (include/lp.h, lp_sim_adc); pulse:
+    device float32 [n_in][len] or None."""
+    cfg = lp_sim_cfg(seed, n_in, noise_words, adc_bits)
+    plen = 0 if pulse is None else int(pulse.shape[-1])
+    check(lib().lp_sim_adc(ctx.h, C.byref(cfg), n0, n_samp, _ptr(pulse),
+                           pulse_n0, plen, _ptr(adc), _stream(stream)))
+
+
+def station_ppf(ctx: Ctx, band: Band, adc, n_in: int, n_frames: int,
+                scale: float, x, work, dtype: int = LP_CI8, stream=None):
+    """Station subbands x [n_sb][n_frames][n_in][2] (int8 or int16) from
+    ADC codes [n_in][(n_frames + 15) * 1024] (include/lp.h)."""
+    check(lib().lp_station_ppf(ctx.h, C.byref(band.c), _ptr(adc), n_in,
+                               n_frames, scale, dtype, _ptr(x), _ptr(work),
+                               work.numel() * work.element_size(),
+                               _stream(stream)))
 
 
 def ppf_analyze(ctx: Ctx, band: Band, x, n_series: int, n_frames: int, y,
