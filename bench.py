@@ -455,13 +455,13 @@ def station_sim_leg(a, ctx, cfg, blk, stream, steps: int = 3):
         from oracle import station_sim
         h = oracle.prototype(1024, 16, 9.0)
         t0 = time.perf_counter()
-        codes = station_sim.adc(1612, 1, 16, 12, 1, (64 + 15) * 1024)
+        codes = station_sim.adc(1612, 1, 16, 12, 1, (1024 + 15) * 1024)
         station_sim.station_ppf(h, 1024, np.asarray(blk.k), codes, scale, 8)
         dt_cpu = time.perf_counter() - t0
         out["cpu_baseline"] = {
-            "value": round(64 * 1024 / dt_cpu / 1e9, 6),
+            "value": round((1024 + 15) * 1024 / dt_cpu / 1e9, 6),
             "unit": "G ADC samples/s", "cores": 1, "kind": "oracle",
-            "sample": "1 input x 64 frames (numpy)",
+            "sample": "1 input x 1024 frames (numpy)",
             "seconds": round(dt_cpu, 2)}
     return out
 
