@@ -10,6 +10,7 @@
 // LP_FP32 does the same sums on the vector ALUs.
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "lp_internal.h"
 
@@ -20,7 +21,6 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBfT = 128;        // time rows per tile
 constexpr int kBfThreads = 256;  // 4 waves
-constexpr int kBfKsMax = 16;     // up to 2K = 256 real rows (K <= 128)
 constexpr size_t kLdsMax = 160 * 1024;
 
 // ------------------------------------------------------------- weights
@@ -103,21 +103,6 @@ __global__ void bf_weights_fp32_kernel(
 
 // --------------------------------------------------------- MFMA kernel
 
-// Vector load of VB bytes into a small register array.
-template <int VB, typename T>
-__device__ __forceinline__ void load_vec(T *dst, const char *src) {
-  if constexpr (VB == 16) {
-    int4 q = *reinterpret_cast<const int4 *>(src);
-    __builtin_memcpy(dst, &q, 16);
-  } else if constexpr (VB == 8) {
-    int2 q = *reinterpret_cast<const int2 *>(src);
-    __builtin_memcpy(dst, &q, 8);
-  } else {
-    int q = *reinterpret_cast<const int *>(src);
-    __builtin_memcpy(dst, &q, 4);
-  }
-}
-
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 
 // Exact int -> FP16 of one 32-bit word: four int8 (as two half2) or two
@@ -146,6 +131,13 @@ __device__ __forceinline__ int word_to_half2(unsigned w, half2v *out) {
   }
 }
 
+// LDS row stride (bytes) of the staged kernel's raw tile: KS*16 samples
+// plus 16 bytes.  For int8 rows the stride in 32-bit words is 4 KS + 4;
+// lanes (row r, quarter kq) then read words r (4 KS + 4) + 4 ks + kq.
+__host__ __device__ inline int bf_row_stride(int KS, int isz) {
+  return KS * 16 * isz + 16;
+}
+
 typedef int intx4 __attribute__((ext_vector_type(4)));
 typedef int intx2 __attribute__((ext_vector_type(2)));
 template <int VB> struct VecT;
@@ -156,20 +148,22 @@ template <> struct VecT<4> { typedef int type; };
 // Grid: x = groups of tiles (T time rows each), y = subband.  Waves are laid
 // out WM x WN over (16-row m-tiles, 16-column n-tiles); each wave keeps its
 // NPW n-tiles of weight fragments in registers for all of its tiles.  The
-// next tile's input is loaded into registers while the current tile is
-// multiplied and stored (up to 128 bytes per thread in flight).
-template <typename IT, int VB, int NPW, int KSM>
+// tile's raw integer rows are staged in LDS as loaded (rows of KS*16
+// samples, zero padded, plus 16 bytes so row-per-lane fragment reads fall
+// on distinct banks) and converted to FP16 as each A fragment is read; the
+// next tile is loaded into registers (NV vectors of VB bytes per thread)
+// while the current one is multiplied and stored.
+template <typename IT, int VB, int NPW, int KSM, int NV>
 __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
     const IT *__restrict__ x, const half4 *__restrict__ wf,
     const _Float16 *__restrict__ xscale, int scaled, float2 *__restrict__ y,
     int n_sb, long n_t, long x_nt, int RK, int KS, int NT, int WN,
     int n_beams, int T, int tiles_per_wg) {
   typedef typename VecT<VB>::type V;
-  constexpr int MAXV = 64 / VB;                  // register vectors per thread
   constexpr int EPV = VB / (int)sizeof(IT);      // samples per vector
-  constexpr int WPV = VB / 4;                    // 32-bit words per vector
-  extern __shared__ _Float16 sm[];
-  const int RKP = KS * 16 + 8;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smb[];
+  const int RSB = bf_row_stride(KS, (int)sizeof(IT));
+  _Float16 *xs_lds = reinterpret_cast<_Float16 *>(smb + T * RSB);
   const int s = blockIdx.y;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -189,57 +183,31 @@ __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
                         : z;
     }
   }
-  // Columns RK .. KS*16-1 multiply zero weights but must not hold NaN
-  // patterns: zero them once (the tiles never write them).
-  const int padc = KS * 16 - RK;
-  for (int i = tid; i < T * padc; i += kBfThreads)
-    sm[(i / padc) * RKP + RK + (i % padc)] = (_Float16)0.0f;
+  // Samples RK .. KS*16-1 of each row multiply zero weights; they are
+  // zeroed once (the tiles never write them), as are the scale factors.
+  const int padb = (KS * 16 - RK) * (int)sizeof(IT);
+  for (int i = tid; i < T * padb; i += kBfThreads)
+    smb[(i / padb) * RSB + RK * (int)sizeof(IT) + (i % padb)] = 0;
+  if (scaled)
+    for (int i = tid; i < KS * 16; i += kBfThreads) xs_lds[i] = xscale[i];
 
-  V pre[MAXV];
+  V pre[NV];
   auto fetch = [&](long t0) {
     const V *src = reinterpret_cast<const V *>(x + ((long)s * x_nt + t0) * RK);
 #pragma unroll
-    for (int i = 0; i < MAXV; ++i) {
+    for (int i = 0; i < NV; ++i) {
       int v = tid + kBfThreads * i;
       if (v < nvec) pre[i] = __builtin_nontemporal_load(src + v);
     }
   };
   auto deposit = [&]() {
 #pragma unroll
-    for (int i = 0; i < MAXV; ++i) {
+    for (int i = 0; i < NV; ++i) {
       int v = tid + kBfThreads * i;
       if (v < nvec) {
         int e0 = v * EPV, row = e0 / RK, col = e0 - row * RK;
-        unsigned w[WPV];
-        __builtin_memcpy(w, &pre[i], VB);
-        half2v h[EPV / 2];
-        int o = 0;
-#pragma unroll
-        for (int q = 0; q < WPV; ++q) o += word_to_half2<IT>(w[q], h + o);
-        if (scaled) {
-#pragma unroll
-          for (int q = 0; q < EPV / 2; ++q) {
-            half2v sc = {xscale[col + 2 * q], xscale[col + 2 * q + 1]};
-            h[q] = h[q] * sc;
-          }
-        }
-        _Float16 *dst = sm + row * RKP + col;
-        if constexpr (EPV % 8 == 0) {
-#pragma unroll
-          for (int q = 0; q < EPV / 8; ++q) {
-            int4 c;
-            __builtin_memcpy(&c, h + 4 * q, 16);
-            *reinterpret_cast<int4 *>(dst + 8 * q) = c;
-          }
-        } else if constexpr (EPV == 4) {
-          int2 c;
-          __builtin_memcpy(&c, h, 8);
-          *reinterpret_cast<int2 *>(dst) = c;
-        } else {
-          int c;
-          __builtin_memcpy(&c, h, 4);
-          *reinterpret_cast<int *>(dst) = c;
-        }
+        *reinterpret_cast<V *>(smb + row * RSB + col * (int)sizeof(IT)) =
+            pre[i];
       }
     }
   };
@@ -258,14 +226,26 @@ __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
     for (int mi = 0; mi < mt_per_wave; ++mi) {
       int mt = wm * mt_per_wave + mi;
       int row = mt * 16 + col16;
+      const unsigned char *rp = smb + row * RSB;
       floatx4 acc[NPW];
 #pragma unroll
       for (int p = 0; p < NPW; ++p) acc[p] = floatx4{0, 0, 0, 0};
 #pragma unroll
       for (int ks = 0; ks < KSM; ++ks) {
         if (ks < KS) {
-          half4 a = *reinterpret_cast<const half4 *>(sm + row * RKP + ks * 16 +
-                                                     4 * kq);
+          // Samples ks*16 + 4*kq .. + 3 of the lane's row.
+          half2v h[2];
+          if constexpr (sizeof(IT) == 1) {
+            word_to_half2<IT>(
+                *reinterpret_cast<const unsigned *>(rp + ks * 16 + 4 * kq), h);
+          } else {
+            uint2 w2 = *reinterpret_cast<const uint2 *>(rp + ks * 32 + 8 * kq);
+            word_to_half2<IT>(w2.x, h);
+            word_to_half2<IT>(w2.y, h + 1);
+          }
+          half4 a = {h[0][0], h[0][1], h[1][0], h[1][1]};
+          if (scaled)
+            a = a * *reinterpret_cast<const half4 *>(xs_lds + ks * 16 + 4 * kq);
 #pragma unroll
           for (int p = 0; p < NPW; ++p)
             acc[p] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, wreg[p][ks],
@@ -512,9 +492,11 @@ static lp_status launch_bf(const BfPlan *p, const void *x, long x_nt,
       return set_error(LP_EINVAL, "beamformer: %d-byte time rows too long",
                        row_bytes);
     const long tiles = n_t / T;
-    const int tpw = tiles >= 8 ? 4 : 1;
+    // Two tiles per workgroup for a single n-tile (less work per tile,
+    // more workgroups in flight), four otherwise: measured on MI355X.
+    const int tpw = tiles >= 8 ? (NT == 1 ? 2 : 4) : 1;
     dim3 grid((unsigned)((tiles + tpw - 1) / tpw), n_sb);
-    size_t shm = (size_t)T * (KS * 16 + 8) * 2;
+    size_t shm = (size_t)T * bf_row_stride(KS, (int)sizeof(IT)) + KS * 32;
     auto args = [&](auto kern) {
       LP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -526,15 +508,35 @@ static lp_status launch_bf(const BfPlan *p, const void *x, long x_nt,
                          NT, WN, p->n_beams, T, tpw);
       return LP_OK;
     };
-    const bool small_k = KS <= 8;
+    // Register arrays sized to the shape: NV load vectors per thread, KSM
+    // weight fragments per n-tile.
+    const int nv = (int)(((long)T * row_bytes / vb + kBfThreads - 1) /
+                         kBfThreads);
     lp_status rc;
-#define LP_BF_PICK(VB_)                                                   \
-    (npw == 1 ? (small_k ? args(bf_mfma_kernel<IT, VB_, 1, 8>)            \
-                         : args(bf_mfma_kernel<IT, VB_, 1, 16>))          \
-              : (small_k ? args(bf_mfma_kernel<IT, VB_, 2, 8>)            \
-                         : args(bf_mfma_kernel<IT, VB_, 2, 16>)))
-    rc = (vb == 16) ? LP_BF_PICK(16) : (vb == 8) ? LP_BF_PICK(8) : LP_BF_PICK(4);
+    if (vb == 16) {
+      auto by_k = [&](auto npw_c, auto nv_c) {
+        constexpr int P_ = decltype(npw_c)::value, V_ = decltype(nv_c)::value;
+        return KS <= 6    ? args(bf_mfma_kernel<IT, 16, P_, 6, V_>)
+               : KS <= 8  ? args(bf_mfma_kernel<IT, 16, P_, 8, V_>)
+               : KS <= 12 ? args(bf_mfma_kernel<IT, 16, P_, 12, V_>)
+                          : args(bf_mfma_kernel<IT, 16, P_, 16, V_>);
+      };
+      using C1 = std::integral_constant<int, 1>;
+      using C2 = std::integral_constant<int, 2>;
+      using C3 = std::integral_constant<int, 3>;
+      using C4 = std::integral_constant<int, 4>;
+      rc = npw == 1 ? (nv <= 3 ? by_k(C1(), C3()) : by_k(C1(), C4()))
+                    : (nv <= 3 ? by_k(C2(), C3()) : by_k(C2(), C4()));
+    } else {
+      const bool small_k = KS <= 8;
+#define LP_BF_PICK(VB_)                                                      \
+    (npw == 1 ? (small_k ? args(bf_mfma_kernel<IT, VB_, 1, 8, 64 / VB_>)     \
+                         : args(bf_mfma_kernel<IT, VB_, 1, 16, 64 / VB_>))   \
+              : (small_k ? args(bf_mfma_kernel<IT, VB_, 2, 8, 64 / VB_>)     \
+                         : args(bf_mfma_kernel<IT, VB_, 2, 16, 64 / VB_>)))
+      rc = (vb == 8) ? LP_BF_PICK(8) : LP_BF_PICK(4);
 #undef LP_BF_PICK
+    }
     if (rc) return rc;
   } else {
     int row_words = row_bytes / 4;
