@@ -221,8 +221,10 @@ __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
     if (t0 >= n_t) break;
     __syncthreads();  // the previous tile's LDS reads are done
     deposit();
-    __syncthreads();
+    // The registers are free once deposited: the next tile's loads go out
+    // before the barrier.
     if (tile + 1 < tiles_per_wg && t0 + T < n_t) fetch(t0 + T);
+    __syncthreads();
     for (int mi = 0; mi < mt_per_wave; ++mi) {
       int mt = wm * mt_per_wave + mi;
       int row = mt * 16 + col16;
