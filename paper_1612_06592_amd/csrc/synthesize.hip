@@ -24,9 +24,9 @@ namespace lp {
 
 constexpr int kSynThreads = 1024;
 
-// Twiddle-table slot of entry n: one pad slot every 8 entries spreads the
-// strided pass-1 reads of a wave over distinct banks.
-__device__ __forceinline__ int twp(int n) { return n + (n >> 3); }
+// Word 3 of a raw (untyped, stride 0) buffer resource on CDNA: 32-bit data
+// format, so bounds-checked dword loads are valid.
+constexpr int kRawBufferWord3 = 0x00020000;
 constexpr int kSynFs = 1089;  // LDS frame stride (>= pad16(1023)+1, odd)
 
 struct SynCand {
@@ -41,7 +41,14 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     SynCand *__restrict__ cand, float *__restrict__ psum, int n_sb, long n_t,
     long frame0, long warm, int F, long cand_nt, long cand_t0) {
   __shared__ float2 lds[16 * kSynFs];
-  __shared__ float2 tw1k[1024 + 128];   // exp(+2 pi i n / 1024) at twp(n)
+  // Twiddles per pass, so every read is a per-chunk base plus a constant
+  // offset (the lanes of one butterfly group read the same entry):
+  //   tw_p1[a][r] = exp(+2 pi i 4 a r / 1024)   (pass 1, a = j mod 16)
+  //   tw_p2[q][t] = exp(+2 pi i (q + 1) t / 1024) (pass 2, t < 256)
+  __shared__ float2 tw_p1[16 * 16];
+  __shared__ float2 tw_p2[3 * 256];
+  // Element offset si * n_t in d of bin j + 64 r (r < 8), or -1 if empty.
+  __shared__ int soff[8 * 64];
   __shared__ float red_s[16];
 
   const int series = blockIdx.y;
@@ -60,10 +67,26 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
 #pragma unroll
   for (int t = 0; t < 16; ++t) win[t] = make_float2(0.f, 0.f);
   {
-    float2 w = tw[4 * tid];
-    tw1k[twp(tid)] = make_float2(w.x, -w.y);
+    // From the table exp(-2 pi i n / 4096), conjugated; every angle index
+    // here is below 1024.
+    int idx;
+    float2 *dst;
+    if (tid < 256) {
+      idx = 4 * (tid >> 4) * (tid & 15);
+      dst = tw_p1 + tid;
+    } else {
+      const int e = tid - 256;
+      idx = (e / 256 + 1) * (e % 256);
+      dst = tw_p2 + e;
+    }
+    const float2 w = tw[4 * idx];
+    *dst = make_float2(w.x, -w.y);
+    if (tid < 512) {
+      const int si = binmap[tid];  // bin (tid % 64) + 64 (tid / 64)
+      soff[tid] = si >= 0 ? si * (int)n_t : -1;
+    }
   }
-  // (the first barrier in the chunk loop orders these writes before use)
+  __syncthreads();
 
   const int n_chunk = F / 16;
   // Pass-0 inputs of a chunk: bins j + 64 r (r < 8; bins >= 512 are empty)
@@ -71,14 +94,28 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
   float2 pre[8];
   auto fetch = [&](long mc_) {
     const int jo = opaque(j), fo = opaque(f);
-    const long m = mc_ + fo;
+    if (mc_ >= 0) {
+      // Inside the block (every chunk but the first of workgroup 0):
+      // 32-bit byte offsets from the series base (n_sb * n_t * 8 < 2^32).
+      const int m = (int)mc_ + fo;
+      const char *db = reinterpret_cast<const char *>(ds);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      int si = binmap[jo + 64 * r];
-      pre[r] = make_float2(0.f, 0.f);
-      if (si >= 0)
-        pre[r] = (m >= 0) ? ds[(long)si * n_t + m]
-                          : hs[si * kSynHist + (kSynHist + m)];
+      for (int r = 0; r < 8; ++r) {
+        const int o = soff[64 * r + jo];
+        pre[r] = make_float2(0.f, 0.f);
+        if (o >= 0)
+          pre[r] = *reinterpret_cast<const float2 *>(db + (unsigned)(o + m) * 8u);
+      }
+    } else {
+      const long m = mc_ + fo;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        int si = binmap[jo + 64 * r];
+        pre[r] = make_float2(0.f, 0.f);
+        if (si >= 0)
+          pre[r] = (m >= 0) ? ds[(long)si * n_t + m]
+                            : hs[si * kSynHist + (kSynHist + m)];
+      }
     }
   };
   fetch(m0 - 16);
@@ -116,9 +153,9 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
 #pragma unroll
       for (int r = 0; r < 16; ++r) v[r] = fr[pad16(jo + 64 * r)];
       {
-        const int jm = (jo & 15) * 4;  // angle 2 pi (j mod 16) r / 256
+        const float2 *twr = tw_p1 + (jo & 15) * 16;  // 2 pi (j mod 16) r / 256
 #pragma unroll
-        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw1k[twp((jm * r) & 1023)]);
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twr[r]);
       }
       dft16<true>(v);
       __syncthreads();
@@ -136,9 +173,9 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
         int jj = jo + 64 * q, jt = jj;
         float2 a0 = fr[pad16(jj)], a1 = fr[pad16(jj + 256)],
                a2 = fr[pad16(jj + 512)], a3 = fr[pad16(jj + 768)];
-        a1 = cmul(a1, tw1k[twp(jt)]);
-        a2 = cmul(a2, tw1k[twp(2 * jt)]);
-        a3 = cmul(a3, tw1k[twp((3 * jt) & 1023)]);
+        a1 = cmul(a1, tw_p2[jt]);
+        a2 = cmul(a2, tw_p2[256 + jt]);
+        a3 = cmul(a3, tw_p2[512 + jt]);
         dft4<true>(a0, a1, a2, a3);
         fr[pad16(jj)] = a0;
         fr[pad16(jj + 256)] = a1;
@@ -157,10 +194,20 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     }
     // Taps are reloaded per chunk (cache hits) so they do not occupy
     // registers during the transform.
+    // A raw buffer view of the 16 x 1024 taps: tap t of column n is at the
+    // constant offset 4096 t plus 4 n, so the loads need no address
+    // arithmetic (offsets past the 64 KB view read as zero).
+    const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float *>(taps), 0, 16 * 1024 * 4, kRawBufferWord3);
     float g[16];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) g[t] = taps[t * 1024 + no];
+    for (int t = 0; t < 16; ++t)
+      g[t] = __uint_as_float(
+          __builtin_amdgcn_raw_buffer_load_b32(trs, 4 * no, 4096 * t, 0));
     float acc_s = 0.f;
+    // Frames before `warm` (stream time) stay out of the statistics.
+    const long fv = warm - (frame0 + mc);
+    const int first_valid = fv <= 0 ? 0 : (fv >= 16 ? 16 : (int)fv);
     float *xo = x_out ? x_out + ((long)series * n_t + mc) * 1024 + no : nullptr;
 #pragma unroll
     for (int fi = 0; fi < 16; ++fi) {
@@ -174,8 +221,7 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
         zi = fmaf(g[t], w.y, zi);
       }
       const float xr = 2.f * zr;
-      const bool valid = (frame0 + mc + fi) >= warm;
-      if (valid) acc_s = fmaf(xr, xr, acc_s);
+      if (fi >= first_valid) acc_s = fmaf(xr, xr, acc_s);
       if (xo) xo[(long)fi * 1024] = xr;
       // The slot is consumed: reuse it for the squared envelope.
       slot->x = 4.f * (zr * zr + zi * zi);
@@ -254,6 +300,10 @@ lp_status syn_launch(lp_ctx *ctx, const SynPlan *p, int n_sb, const void *d,
                      int n_series, long n_t, long frame0, void *hist,
                      float *x_out, void *cand, long cand_nt, long cand_t0,
                      hipStream_t st) {
+  // The kernel addresses one series' subbands with 32-bit byte offsets.
+  if ((long)n_sb * n_t * 8 >= (1L << 32))
+    return set_error(LP_EINVAL, "synthesis: %d subbands x %ld frames too large",
+                     n_sb, n_t);
   // Frames per workgroup: long blocks amortise the 16-frame warm-up; short
   // ones keep enough workgroups to fill the chip.
   int F = 256;
