@@ -150,8 +150,10 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     // ---- pass 1 (radix 16, Ns = 16).
     {
       float2 *fr = lds + fo * kSynFs;
+      // pad16(j + 64 r) = j + j / 16 + 68 r for j < 64.
+      const int b1 = jo + (jo >> 4);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = fr[pad16(jo + 64 * r)];
+      for (int r = 0; r < 16; ++r) v[r] = fr[b1 + 68 * r];
       {
         const float2 *twr = tw_p1 + (jo & 15) * 16;  // 2 pi (j mod 16) r / 256
 #pragma unroll
@@ -159,28 +161,31 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
       }
       dft16<true>(v);
       __syncthreads();
-      int base = (jo >> 4) * 256 + (jo & 15);
+      // pad16((j / 16) 256 + j mod 16 + 16 r) = (j / 16) 272 + j mod 16 + 17 r.
+      const int b2 = (jo >> 4) * 272 + (jo & 15);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) fr[pad16(base + 16 * r)] = v[r];
+      for (int r = 0; r < 16; ++r) fr[b2 + 17 * r] = v[r];
     }
     __syncthreads();
     // ---- pass 2 (radix 4, Ns = 256): butterflies j + 64 q, q < 4; each
     // reads and writes the same four slots, so no barrier in between.
     {
       float2 *fr = lds + fo * kSynFs;
+      // Slot pad16(j + 64 q + 256 k) = j + j / 16 + 68 q + 272 k (j < 64).
+      const int b1 = jo + (jo >> 4);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        int jj = jo + 64 * q, jt = jj;
-        float2 a0 = fr[pad16(jj)], a1 = fr[pad16(jj + 256)],
-               a2 = fr[pad16(jj + 512)], a3 = fr[pad16(jj + 768)];
+        const int jt = jo + 64 * q;
+        float2 *sl = fr + b1 + 68 * q;
+        float2 a0 = sl[0], a1 = sl[272], a2 = sl[544], a3 = sl[816];
         a1 = cmul(a1, tw_p2[jt]);
         a2 = cmul(a2, tw_p2[256 + jt]);
         a3 = cmul(a3, tw_p2[512 + jt]);
         dft4<true>(a0, a1, a2, a3);
-        fr[pad16(jj)] = a0;
-        fr[pad16(jj + 256)] = a1;
-        fr[pad16(jj + 512)] = a2;
-        fr[pad16(jj + 768)] = a3;
+        sl[0] = a0;
+        sl[272] = a1;
+        sl[544] = a2;
+        sl[816] = a3;
       }
     }
     __syncthreads();
@@ -233,17 +238,20 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     // Wave w finds the envelope maximum of frame w (lowest n on ties).
     {
       const float2 *fr = lds + wo * kSynFs;
+      // Lane l scans n = l + 64 i (slot pad16(n) = l + l / 16 + 68 i),
+      // keeping the first i of its maximum.
       float bv = -1.f;
-      int bi = 0;
+      int bk = 0;
+      const float2 *fl = fr + lo + (lo >> 4);
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        int nn = lo + 64 * i;
-        float e2 = fr[pad16(nn)].x;
+        float e2 = fl[68 * i].x;
         if (e2 > bv) {
           bv = e2;
-          bi = nn;
+          bk = i;
         }
       }
+      int bi = lo + 64 * bk;
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
         float ov = __shfl_xor(bv, off);
