@@ -91,6 +91,19 @@ __global__ void dd_consts_kernel(const double *__restrict__ tec,
   if (j == 0) rfk[s] = (float)(df / (double)kNfft / fk);
 }
 
+// The trial-independent factor of the chirp phase, per subband and bin:
+// g = x / (1 + x) with x = nu_q / f_k and nu_q = q_s (subband rate / N_fft).
+__global__ void dd_ratio_kernel(const int *__restrict__ k, int n_sb, double f0,
+                                double df, float *__restrict__ gq) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n_sb * kNfft) return;
+  const int s = (int)(i / kNfft), q = (int)(i % kNfft);
+  const int qs = q < kNfft / 2 ? q : q - kNfft;
+  const double fk = f0 + (double)k[s] * df;
+  const double x = (double)qs * (df / (double)kNfft) / fk;
+  gq[i] = (float)(x / (1.0 + x));
+}
+
 lp_status get_dd_plan(lp_ctx *ctx, const lp_band *band, const double *tec,
                       int n_tec, DdPlan **out) {
   std::vector<uint8_t> key;
@@ -111,6 +124,7 @@ lp_status get_dd_plan(lp_ctx *ctx, const lp_band *band, const double *tec,
   LP_HIP(hipMalloc(&p->base.p, js * 4));
   LP_HIP(hipMalloc(&p->afac.p, js * 4));
   LP_HIP(hipMalloc(&p->rfk.p, band->n_sb * 4));
+  LP_HIP(hipMalloc(&p->gq.p, (size_t)band->n_sb * kNfft * 4));
   DevBuf dtec, dk;
   LP_HIP(hipMalloc(&dtec.p, n_tec * 8));
   LP_HIP(hipMalloc(&dk.p, band->n_sb * 4));
@@ -122,6 +136,11 @@ lp_status get_dd_plan(lp_ctx *ctx, const lp_band *band, const double *tec,
                      band->f0_hz, band->fs_hz / kM, kappa_per_tecu(),
                      p->base.as<float>(), p->afac.as<float>(),
                      p->rfk.as<float>());
+  LP_HIP(hipGetLastError());
+  const long ng = (long)band->n_sb * kNfft;
+  hipLaunchKernelGGL(dd_ratio_kernel, dim3((unsigned)((ng + 255) / 256)),
+                     dim3(256), 0, 0, dk.as<int>(), band->n_sb, band->f0_hz,
+                     band->fs_hz / kM, p->gq.as<float>());
   LP_HIP(hipGetLastError());
   LP_HIP(hipDeviceSynchronize());
   *out = p.get();

@@ -58,15 +58,19 @@ template <bool INV>
 __device__ __forceinline__ void fft4096(float2 *v, float2 *lds,
                                         const float2 *coarse,
                                         const float2 *fine, int j) {
+  // LDS slots in closed form (j < 256, r < 16):
+  //   pad16(16 j + r) = 17 j + r,  pad16(j + 256 r) = j + j / 16 + 272 r,
+  //   pad16((j / 16) 256 + j mod 16 + 16 r) = (j / 16) 272 + j mod 16 + 17 r.
+  const int sj = j + (j >> 4);
   // Pass 0 (Ns = 1): no twiddle; write to (16 j + r).
   dft16<INV>(v);
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 16; ++r) lds[pad16(16 * j + r)] = v[r];
+  for (int r = 0; r < 16; ++r) lds[17 * j + r] = v[r];
   __syncthreads();
   // Pass 1 (Ns = 16).
 #pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = lds[pad16(j + 256 * r)];
+  for (int r = 0; r < 16; ++r) v[r] = lds[sj + 272 * r];
   {
     const float2 w = coarse[j & 15];  // angle 2 pi (j mod 16) / 256
     pow16_twiddle(v, INV ? make_float2(w.x, -w.y) : w);
@@ -74,14 +78,14 @@ __device__ __forceinline__ void fft4096(float2 *v, float2 *lds,
   dft16<INV>(v);
   __syncthreads();
   {
-    int base = (j >> 4) * 256 + (j & 15);
+    const int b2 = (j >> 4) * 272 + (j & 15);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) lds[pad16(base + 16 * r)] = v[r];
+    for (int r = 0; r < 16; ++r) lds[b2 + 17 * r] = v[r];
   }
   __syncthreads();
   // Pass 2 (Ns = 256): output index j + 256 r stays in registers.
 #pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = lds[pad16(j + 256 * r)];
+  for (int r = 0; r < 16; ++r) v[r] = lds[sj + 272 * r];
   pow16_twiddle(v, tw4096_lds<INV>(coarse, fine, j));
   dft16<INV>(v);
 }
@@ -91,7 +95,7 @@ __attribute__((amdgpu_waves_per_eu(4, 8))) void dd_kernel(
     const float2 *__restrict__ y, float2 *__restrict__ tail, int update_tail,
     float2 *__restrict__ d, const float2 *__restrict__ tw,
     const float *__restrict__ base, const float *__restrict__ afac,
-    const float *__restrict__ rfk, int n_sb, int n_tec, long n_t, int n_hop,
+    const float *__restrict__ gq, int n_sb, int n_tec, long n_t, int n_hop,
     long n_blocks) {
   __shared__ float2 lds[kDdLds];
   __shared__ float2 coarse[256], fine[16];
@@ -127,22 +131,25 @@ __attribute__((amdgpu_waves_per_eu(4, 8))) void dd_kernel(
   float2 U[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) U[r] = v[r];
-  const float rf = rfk[s];
+  // Chirp phase of bin q (signed q_s) for trial t, in cycles:
+  //   frac(kappa T / (f_k + nu_q)) + q_s D / 4096
+  //     = frac(A) - A g_q + (q_s mod 4) / 4   (mod 1),
+  // with A = kappa T / f_k, g_q = x / (1 + x), x = nu_q / f_k from the plan
+  // table, and q_s mod 4 = j mod 4 for every bin of thread j.  The residual
+  // A g_q is below ~0.4 cycles; the hardware sine/cosine take revolutions.
+  const __amdgpu_buffer_rsrc_t grs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float *>(gq), 0, n_sb * kNfft * 4, kRawBufferWord3);
+  const float e = 0.25f * (float)(j & 3);
   const float scale = 1.0f / 4096.0f;
   for (int jt = 0; jt < n_tec; ++jt) {
     const int jo = opaque(j);
-    const float bse = base[jt * n_sb + s], A = afac[jt * n_sb + s];
+    const float bse = base[jt * n_sb + s] + e, A = afac[jt * n_sb + s];
+    const int goff = 4 * (s * kNfft + jo);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      int q = jo + 256 * r;
-      int qs = (q < 2048) ? q : q - 4096;
-      float x = (float)qs * rf;                     // nu_q / f_k
-      // frac(kappa T/(f_k+nu)) = frac(A) - A x / (1 + x); the bulk delay
-      // q_s D / 4096 = q_s / 4 contributes (q_s mod 4) / 4 exactly.
-      // The residual is below ~0.4 cycles, so a 1-ulp reciprocal adds < 1e-7
-      // cycles; the hardware sine/cosine take the phase in revolutions.
-      float c = bse - A * x * __builtin_amdgcn_rcpf(1.0f + x) +
-                0.25f * (float)(qs & 3);
+      const float g = __uint_as_float(
+          __builtin_amdgcn_raw_buffer_load_b32(grs, goff, 1024 * r, 0));
+      float c = fmaf(-A, g, bse);
       c -= rintf(c);
       const float sn = __builtin_amdgcn_sinf(c), cs = __builtin_amdgcn_cosf(c);
       v[r] = cmul(U[r], make_float2(cs, -sn));
@@ -203,7 +210,7 @@ lp_status dd_launch(lp_ctx *ctx, const DdPlan *p, int n_sb, const void *y,
                      static_cast<const float2 *>(y), static_cast<float2 *>(tail),
                      update_tail ? 1 : 0, static_cast<float2 *>(d),
                      ctx->tw4096.as<const float2>(), p->base.as<const float>(),
-                     p->afac.as<const float>(), p->rfk.as<const float>(), n_sb,
+                     p->afac.as<const float>(), p->gq.as<const float>(), n_sb,
                      p->n_tec, n_t, n_hop, nb);
   LP_HIP(hipGetLastError());
   return LP_OK;

@@ -63,6 +63,7 @@ struct DdPlan {
   DevBuf base;   // f32 [J][S] frac(kappa T / f_k) in cycles
   DevBuf afac;   // f32 [J][S] kappa T / f_k in cycles
   DevBuf rfk;    // f32 [S] (subband rate / N_fft) / f_k
+  DevBuf gq;     // f32 [S][N_fft] x / (1 + x), x = nu_q / f_k (signed bin q)
 };
 
 // Synthesis tables for one (band, prototype beta).
@@ -96,6 +97,11 @@ struct lp_ctx {
 };
 
 namespace lp {
+
+// Word 3 of a raw (untyped, stride 0) buffer resource on CDNA: 32-bit data
+// format, so bounds-checked dword loads are valid (offsets past the
+// resource's size read as zero).
+constexpr int kRawBufferWord3 = 0x00020000;
 
 // Beamformer input shapes every launch supports: at most 128 inputs, a
 // time row (n_in complex samples) a multiple of 4 bytes, and on the

@@ -24,9 +24,6 @@ namespace lp {
 
 constexpr int kSynThreads = 1024;
 
-// Word 3 of a raw (untyped, stride 0) buffer resource on CDNA: 32-bit data
-// format, so bounds-checked dword loads are valid.
-constexpr int kRawBufferWord3 = 0x00020000;
 constexpr int kSynFs = 1089;  // LDS frame stride (>= pad16(1023)+1, odd)
 
 struct SynCand {
