@@ -157,8 +157,8 @@ template <typename IT, int VB, int NPW, int KSM, int NV>
 __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
     const IT *__restrict__ x, const half4 *__restrict__ wf,
     const _Float16 *__restrict__ xscale, int scaled, float2 *__restrict__ y,
-    int n_sb, long n_t, long x_nt, int RK, int KS, int NT, int WN,
-    int n_beams, int T, int tiles_per_wg) {
+    int n_sb, long n_t, long x_nt, int RK, int KS, int NT, int wn_shift,
+    int n_beams, int T, int tiles_per_wg, float inv_vpr) {
   typedef typename VecT<VB>::type V;
   constexpr int EPV = VB / (int)sizeof(IT);      // samples per vector
   extern __shared__ __attribute__((aligned(16))) unsigned char smb[];
@@ -167,9 +167,12 @@ __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
   const int s = blockIdx.y;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int wn = wave % WN, wm = wave / WN, WM = 4 / WN;
+  // WN = 2^wn_shift waves across n-tiles, WM = 4 / WN across m-tiles.
+  const int WN = 1 << wn_shift;
+  const int wn = wave & (WN - 1), wm = wave >> wn_shift;
   const int kq = lane >> 4, col16 = lane & 15;
   const int nvec = T * RK / EPV;
+  const int vpr = RK / EPV;  // load vectors per time row
 
   half4 wreg[NPW][KSM];
 #pragma unroll
@@ -191,31 +194,41 @@ __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
   if (scaled)
     for (int i = tid; i < KS * 16; i += kBfThreads) xs_lds[i] = xscale[i];
 
+  // LDS byte offset of each of this thread's load vectors within a tile
+  // (the same for every tile; -1 past the tile).  row = v / vpr through
+  // the float reciprocal: exact, since v < 2^12 and the product's error is
+  // far below the 0.5 / vpr margin.
+  int loff[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int v = tid + kBfThreads * i;
+    const int row = (int)(((float)v + 0.5f) * inv_vpr);
+    loff[i] = v < nvec ? row * RSB + (v - row * vpr) * VB : -1;
+  }
   V pre[NV];
   auto fetch = [&](long t0) {
-    const V *src = reinterpret_cast<const V *>(x + ((long)s * x_nt + t0) * RK);
+    // Uniform tile base plus 32-bit per-thread offsets (a tile is at most
+    // 16 KB).
+    const char *src = reinterpret_cast<const char *>(x) +
+                      ((long)s * x_nt + t0) * RK * (long)sizeof(IT);
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      int v = tid + kBfThreads * i;
-      if (v < nvec) pre[i] = __builtin_nontemporal_load(src + v);
+      const unsigned v = tid + kBfThreads * i;
+      if (loff[i] >= 0)
+        pre[i] = __builtin_nontemporal_load(
+            reinterpret_cast<const V *>(src + v * (unsigned)VB));
     }
   };
   auto deposit = [&]() {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      int v = tid + kBfThreads * i;
-      if (v < nvec) {
-        int e0 = v * EPV, row = e0 / RK, col = e0 - row * RK;
-        *reinterpret_cast<V *>(smb + row * RSB + col * (int)sizeof(IT)) =
-            pre[i];
-      }
-    }
+    for (int i = 0; i < NV; ++i)
+      if (loff[i] >= 0) *reinterpret_cast<V *>(smb + loff[i]) = pre[i];
   };
 
   const long tile0 = (long)blockIdx.x * tiles_per_wg;
   if (tile0 * T >= n_t) return;
   fetch(tile0 * T);
-  const int mt_per_wave = (T / 16) / WM;
+  const int mt_per_wave = (T >> 4) >> (2 - wn_shift);
   for (int tile = 0; tile < tiles_per_wg; ++tile) {
     const long t0 = (tile0 + tile) * T;
     if (t0 >= n_t) break;
@@ -484,7 +497,8 @@ static lp_status launch_bf(const BfPlan *p, const void *x, long x_nt,
   const int vb = (row_bytes % 16 == 0) ? 16 : (row_bytes % 8 == 0) ? 8 : 4;
   if (p->prec == LP_FP16_MFMA) {
     const int NT = p->NT, KS = p->KS;
-    const int WN = (NT == 1) ? 1 : (NT == 2) ? 2 : 4;
+    const int wn_shift = (NT == 1) ? 0 : (NT == 2) ? 1 : 2;
+    const int WN = 1 << wn_shift;
     const int npw = (NT + WN - 1) / WN;
     // Rows per tile: at most 64 bytes of input per thread (the prefetch
     // registers), a multiple of 64 rows so the m-tiles split over waves.
@@ -507,7 +521,8 @@ static lp_status launch_bf(const BfPlan *p, const void *x, long x_nt,
                          static_cast<const IT *>(x), p->w.as<const half4>(),
                          p->xscale.as<const _Float16>(), (int)p->scaled,
                          static_cast<float2 *>(y), n_sb, n_t, x_nt, RK, KS,
-                         NT, WN, p->n_beams, T, tpw);
+                         NT, wn_shift, p->n_beams, T, tpw,
+                         1.0f / (float)(row_bytes / vb));
       return LP_OK;
     };
     // Register arrays sized to the shape: NV load vectors per thread, KSM

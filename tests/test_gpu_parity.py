@@ -248,4 +248,11 @@ def test_invalid_arguments_rejected():
     with pytest.raises(lp.LpError):
         lp.synthesize(ctx, bad, p.bufs["d"], 1, 4096, 0, p.bufs["hist"],
                       p.bufs["cand"])
+    # One series of 256 subbands x 2^21 frames is 2^32 bytes: beyond the
+    # synthesis kernel's 32-bit offsets, rejected before any launch.
+    wide = lp.Band(np.arange(1, 257))
+    with pytest.raises(lp.LpError) as e:
+        lp.synthesize(ctx, wide, p.bufs["d"], 1, 1 << 21, 0, p.bufs["hist"],
+                      p.bufs["cand"])
+    assert "too large" in str(e.value)
     ctx.close()
