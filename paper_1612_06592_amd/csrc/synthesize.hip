@@ -40,9 +40,11 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
   __shared__ float2 lds[16 * kSynFs];
   // Twiddles per pass, so every read is a per-chunk base plus a constant
   // offset (the lanes of one butterfly group read the same entry):
-  //   tw_p1[a][r] = exp(+2 pi i 4 a r / 1024)   (pass 1, a = j mod 16)
+  //   tw_p1[a][r] = exp(+2 pi i 4 a r / 1024)   (pass 1, a = j mod 16;
+  //                 rows of 17 so the 16 rows a wave reads fall on distinct
+  //                 banks)
   //   tw_p2[q][t] = exp(+2 pi i (q + 1) t / 1024) (pass 2, t < 256)
-  __shared__ float2 tw_p1[16 * 16];
+  __shared__ float2 tw_p1[16 * 17];
   __shared__ float2 tw_p2[3 * 256];
   // Element offset si * n_t in d of bin j + 64 r (r < 8), or -1 if empty.
   __shared__ int soff[8 * 64];
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     float2 *dst;
     if (tid < 256) {
       idx = 4 * (tid >> 4) * (tid & 15);
-      dst = tw_p1 + tid;
+      dst = tw_p1 + (tid >> 4) * 17 + (tid & 15);
     } else {
       const int e = tid - 256;
       idx = (e / 256 + 1) * (e % 256);
@@ -144,35 +146,36 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
         hs[i] = ds[(long)si * n_t + (n_t - kSynHist + fi)];
       }
     }
-    // ---- pass 1 (radix 16, Ns = 16).
+    // ---- passes 1 and 2: wave w transforms frame w alone (lane = butterfly
+    // j), so the exchange between the passes stays inside the wave: its LDS
+    // operations execute in issue order, and the fence below only keeps the
+    // compiler from moving the pass-2 reads above the pass-1 writes.
     {
-      float2 *fr = lds + fo * kSynFs;
+      float2 *fr = lds + wo * kSynFs;
       // pad16(j + 64 r) = j + j / 16 + 68 r for j < 64.
-      const int b1 = jo + (jo >> 4);
+      const int b1 = lo + (lo >> 4);
+      // ---- pass 1 (radix 16, Ns = 16).
 #pragma unroll
       for (int r = 0; r < 16; ++r) v[r] = fr[b1 + 68 * r];
       {
-        const float2 *twr = tw_p1 + (jo & 15) * 16;  // 2 pi (j mod 16) r / 256
+        const float2 *twr = tw_p1 + (lo & 15) * 17;  // 2 pi (j mod 16) r / 256
 #pragma unroll
         for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twr[r]);
       }
       dft16<true>(v);
-      __syncthreads();
       // pad16((j / 16) 256 + j mod 16 + 16 r) = (j / 16) 272 + j mod 16 + 17 r.
-      const int b2 = (jo >> 4) * 272 + (jo & 15);
+      const int b2 = (lo >> 4) * 272 + (lo & 15);
 #pragma unroll
       for (int r = 0; r < 16; ++r) fr[b2 + 17 * r] = v[r];
-    }
-    __syncthreads();
-    // ---- pass 2 (radix 4, Ns = 256): butterflies j + 64 q, q < 4; each
-    // reads and writes the same four slots, so no barrier in between.
-    {
-      float2 *fr = lds + fo * kSynFs;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // ---- pass 2 (radix 4, Ns = 256): butterflies j + 64 q, q < 4; each
+      // reads and writes the same four slots.
       // Slot pad16(j + 64 q + 256 k) = j + j / 16 + 68 q + 272 k (j < 64).
-      const int b1 = jo + (jo >> 4);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int jt = jo + 64 * q;
+        const int jt = lo + 64 * q;
         float2 *sl = fr + b1 + 68 * q;
         float2 a0 = sl[0], a1 = sl[272], a2 = sl[544], a3 = sl[816];
         a1 = cmul(a1, tw_p2[jt]);
