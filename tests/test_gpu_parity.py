@@ -172,6 +172,30 @@ def test_odd_shapes_and_ci16_mfma():
         _check_block(g, o, prec, keep=(0, 2), label=f"odd prec={prec}")
 
 
+@pytest.mark.parametrize("n_st", [3, 6])
+def test_beamform_narrow_int8_rows(n_st):
+    """int8 rows that are not a multiple of 16 bytes (3 stations: 12-byte
+    rows, loaded as 4-byte vectors; 6 stations: 24-byte rows, 8-byte
+    vectors), zero-padded to a 16-sample k-step, on both precisions."""
+    cfg = lofarsim.get_config("c2", n_st=n_st, hex_rings=1, n_t=1024,
+                              k=tuple(range(52, 61)), n_pulses=0)
+    blk = lofarsim.generate(cfg)
+    assert blk.x.dtype == np.int8 and (2 * 2 * n_st) % 16 != 0
+    import oracle
+    import torch
+    from chain import as_complex, gpu_pipeline, to_device
+    ref = oracle.beamform(blk.enu, 2, blk.k, blk.az_el, blk.x)
+    for prec in (lp.LP_FP16_MFMA, lp.LP_FP32):
+        print("case bf-narrow n_st", n_st, "prec", prec, flush=True)
+        ctx, p = gpu_pipeline(blk, prec, want_series=False)
+        p.beamform(to_device(blk.x))
+        torch.cuda.synchronize()
+        e = rel_rms(as_complex(p.y_view()), ref)
+        ctx.close()
+        print("bf-narrow prec", prec, "rel-rms", e, flush=True)
+        assert e <= TOL[prec]
+
+
 def test_stream_state_carry_bitwise():
     """Two consecutive blocks through carried state equal one long block
     (bitwise for every sample-local output)."""
