@@ -57,35 +57,77 @@ struct LsmrState {
 };
 static_assert(sizeof(LsmrState) <= kPpfStateBytes, "state size");
 
-// Passes 1 and 2 of a 1024-point Stockham transform (radix 16 with
-// Ns = 16, radix 4 with Ns = 256) on LDS frame fr, whose pass-0 output is
-// in place; thread j < 64 of the frame.  Ends with the natural-order
-// result in fr, after a barrier.  tw1k[n] = exp(+2 pi i n / 1024); INV
-// selects the +i kernel.
-template <bool INV>
-__device__ __forceinline__ void fft1024_tail(float2 *fr,
-                                             const float2 *tw1k, int j) {
+// Twiddle tables of the wave-local transform (filled once per workgroup
+// from the table exp(-2 pi i n / 4096), conjugated; every angle index is
+// below 1024):
+//   tw_p1[a][r] = exp(+2 pi i 4 a r / 1024), rows of 17 entries so the 16
+//                 rows one wave reads fall on distinct banks;
+//   tw_p2[q][t] = exp(+2 pi i (q + 1) t / 1024), t < 256.
+constexpr int kTwP1 = 16 * 17, kTwP2 = 3 * 256;
+__device__ __forceinline__ void fill_tw_tables(const float2 *tw,
+                                               float2 *tw_p1, float2 *tw_p2) {
+  const int tid = threadIdx.x;
+  int idx;
+  float2 *dst;
+  if (tid < 256) {
+    idx = 4 * (tid >> 4) * (tid & 15);
+    dst = tw_p1 + (tid >> 4) * 17 + (tid & 15);
+  } else {
+    const int e = tid - 256;
+    idx = (e / 256 + 1) * (e % 256);
+    dst = tw_p2 + e;
+  }
+  const float2 w = tw[4 * idx];
+  *dst = make_float2(w.x, -w.y);
+}
+
+// A wavefront-scope fence: the wave's LDS operations execute in order, so
+// this only keeps the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The 1024-point Stockham transform (radix 16, 16, 4) of LDS frame fr by
+// one wave, lane j = butterfly: PASS0 also runs pass 0 on the frame in
+// natural order; otherwise pass 0's output is already in place.  No
+// workgroup barrier: the caller orders the frame's producers before and
+// its consumers after.  Slots in closed form (j < 64):
+//   pad16(j + 64 r) = j + j / 16 + 68 r,   pad16(16 j + r) = 17 j + r,
+//   pad16((j / 16) 256 + j mod 16 + 16 r) = (j / 16) 272 + j mod 16 + 17 r.
+template <bool INV, bool PASS0>
+__device__ __forceinline__ void fft1024_wave(float2 *fr, const float2 *tw_p1,
+                                             const float2 *tw_p2, int j) {
+  const int b1 = j + (j >> 4);
   float2 v[16];
+  if constexpr (PASS0) {
 #pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = fr[pad16(j + 64 * r)];
-  const int jm = (j & 15) * 4;  // angle 2 pi (j mod 16) r / 256
+    for (int r = 0; r < 16; ++r) v[r] = fr[b1 + 68 * r];
+    dft16<INV>(v);
 #pragma unroll
-  for (int r = 1; r < 16; ++r) {
-    float2 w = tw1k[(jm * r) & 1023];
-    v[r] = INV ? cmul(v[r], w) : cmulc(v[r], w);
+    for (int r = 0; r < 16; ++r) fr[17 * j + r] = v[r];
+    wave_lds_fence();
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = fr[b1 + 68 * r];
+  {
+    const float2 *twr = tw_p1 + (j & 15) * 17;  // 2 pi (j mod 16) r / 256
+#pragma unroll
+    for (int r = 1; r < 16; ++r)
+      v[r] = INV ? cmul(v[r], twr[r]) : cmulc(v[r], twr[r]);
   }
   dft16<INV>(v);
-  __syncthreads();
-  const int base = (j >> 4) * 256 + (j & 15);
+  const int b2 = (j >> 4) * 272 + (j & 15);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) fr[pad16(base + 16 * r)] = v[r];
-  __syncthreads();
+  for (int r = 0; r < 16; ++r) fr[b2 + 17 * r] = v[r];
+  wave_lds_fence();
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int jj = j + 64 * q;
-    float2 a0 = fr[pad16(jj)], a1 = fr[pad16(jj + 256)],
-           a2 = fr[pad16(jj + 512)], a3 = fr[pad16(jj + 768)];
-    const float2 w1 = tw1k[jj], w2 = tw1k[2 * jj], w3 = tw1k[3 * jj];
+    const int jt = j + 64 * q;
+    float2 *sl = fr + b1 + 68 * q;
+    float2 a0 = sl[0], a1 = sl[272], a2 = sl[544], a3 = sl[816];
+    const float2 w1 = tw_p2[jt], w2 = tw_p2[256 + jt], w3 = tw_p2[512 + jt];
     if (INV) {
       a1 = cmul(a1, w1);
       a2 = cmul(a2, w2);
@@ -96,12 +138,11 @@ __device__ __forceinline__ void fft1024_tail(float2 *fr,
       a3 = cmulc(a3, w3);
     }
     dft4<INV>(a0, a1, a2, a3);
-    fr[pad16(jj)] = a0;
-    fr[pad16(jj + 256)] = a1;
-    fr[pad16(jj + 512)] = a2;
-    fr[pad16(jj + 768)] = a3;
+    sl[0] = a0;
+    sl[272] = a1;
+    sl[544] = a2;
+    sl[816] = a3;
   }
-  __syncthreads();
 }
 
 // Sum of one value per thread of a 1024-thread workgroup, fixed order;
@@ -135,7 +176,7 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_fwd_kernel(
     const float2 *__restrict__ tw, int n_sb, long nf, int n_part,
     float oscale = 1.f, int olim = 0, short2 *__restrict__ sout = nullptr) {
   __shared__ float2 lds[16 * kPpfFs];
-  __shared__ float2 tw1k[1024];
+  __shared__ float2 tw_p1[kTwP1], tw_p2[kTwP2];
   __shared__ float red[16];
 
   const int series = blockIdx.y;
@@ -153,10 +194,7 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_fwd_kernel(
   const long vbase = (long)series * N;
   const float2 *yi = yin + (long)series * n_sb * nf;
   float2 *yo = yout + (long)series * n_sb * nf;
-  {
-    float2 w = tw[4 * tid];  // exp(-2 pi i tid / 1024)
-    tw1k[tid] = make_float2(w.x, -w.y);
-  }
+  fill_tw_tables(tw, tw_p1, tw_p2);  // used after the first FIR barrier
   // Taps are g = 1024 h: fold 1 / 1024 into the input scale (exact).
   float ps = 1.f, qs = 0.f, c_hbar = 0.f, c_x = 0.f, c_h = 0.f;
   int first = 0;
@@ -183,7 +221,8 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_fwd_kernel(
   for (int c = 0; c < kPpfWg / kPpfChunk; ++c) {
     const long mc = m0 + (long)c * kPpfChunk;
     if (mc >= nf) break;
-    const int ro = opaque(tid), jo = opaque(j), fo = opaque(f);
+    const int ro = opaque(tid);
+    const int lo = opaque(tid & 63), wo = opaque(tid >> 6);
     float g[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) g[t] = taps[t * kM + ro];
@@ -236,19 +275,10 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_fwd_kernel(
       }
     }
     __syncthreads();
-    // ---- Transform of the 16 packed frames: v_e + i v_o.
-    {
-      float2 *fr = lds + fo * kPpfFs;
-      float2 v[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) v[q] = fr[pad16(jo + 64 * q)];
-      dft16<true>(v);
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 16; ++q) fr[pad16(16 * jo + q)] = v[q];
-      __syncthreads();
-      fft1024_tail<true>(fr, tw1k, jo);
-    }
+    // ---- Transform of the 16 packed frames v_e + i v_o: wave w transforms
+    // packed frame w.
+    fft1024_wave<true, true>(lds + wo * kPpfFs, tw_p1, tw_p2, lo);
+    __syncthreads();
     // ---- Recorded bins of both frames of each pair:
     //   Y_even = (C_k + conj C_{M-k}) / 2,  Y_odd = (C_k - conj C_{M-k}) / 2i.
     for (int it = tid; it < 16 * n_sb; it += kPpfThreads) {
@@ -305,7 +335,7 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_adj_kernel(
     const short *__restrict__ binmap, const float *__restrict__ taps,
     const float2 *__restrict__ tw, int n_sb, long nf, int n_part) {
   __shared__ float2 lds[16 * kPpfFs];
-  __shared__ float2 tw1k[1024];
+  __shared__ float2 tw_p1[kTwP1], tw_p2[kTwP2];
   __shared__ float red[16];
 
   const int series = blockIdx.y;
@@ -318,10 +348,7 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_adj_kernel(
   const int f = tid & 15, j = tid >> 4;
   const float2 *yi = yin + (long)series * n_sb * nf;
   float *po = pio + (long)series * N;
-  {
-    float2 w = tw[4 * tid];
-    tw1k[tid] = make_float2(w.x, -w.y);
-  }
+  fill_tw_tables(tw, tw_p1, tw_p2);  // used after the first pass-0 barrier
   // Packing halves, taps g = 1024 h: both folded into the input scale.
   float is = 0.5f / 1024.f, vs = 0.f;
   if (MODE == kAdjLsmr) {
@@ -336,6 +363,7 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_adj_kernel(
   for (int c = 0; c < n_chunk; ++c) {
     const long mc = j0 + (long)c * kPpfChunk;
     const int jo = opaque(j), fo = opaque(f), ro = opaque(tid);
+    const int lo = opaque(tid & 63), wo = opaque(tid >> 6);
     // ---- Packed spectrum of frames mc + 2f, mc + 2f + 1: at bin k,
     // (u_even + i u_odd) / 2; at bin 1024 - k, (conj u_even + i conj
     // u_odd) / 2; zero elsewhere.  Pass 0 reads bins jo + 64 q.
@@ -365,9 +393,11 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_adj_kernel(
     {
       float2 *fr = lds + fo * kPpfFs;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) fr[pad16(16 * jo + q)] = v[q];
+      for (int q = 0; q < 16; ++q) fr[17 * jo + q] = v[q];  // pad16(16 j + q)
       __syncthreads();
-      fft1024_tail<false>(fr, tw1k, jo);
+      // Passes 1 and 2: wave w transforms frame w.
+      fft1024_wave<false, false>(lds + wo * kPpfFs, tw_p1, tw_p2, lo);
+      __syncthreads();
     }
     // ---- Anti-causal FIR: frame jj = m - 15 once W_m has arrived.
     float g[16];
