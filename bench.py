@@ -95,9 +95,10 @@ def main():
                          "calibrating HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (the hot path "
-              "shards by beam or TEC trial with a broadcast of the station "
-              "block; that multi-GPU path is not built)", file=sys.stderr)
+        print("bench.py: the library runs on one GPU only (the hot path "
+              "would shard by beam or TEC trial with a broadcast of the "
+              "station block; that multi-GPU path is not implemented)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
