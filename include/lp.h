@@ -284,7 +284,8 @@ lp_status lp_synthesize_plain(lp_ctx *ctx, const lp_band *band, const void *d,
  * Layouts (device memory, caller-owned): y and d are complex float
  * [n_series][n_sb][n_frames] (the layout lp_dedisperse writes: series =
  * beam * n_tec + trial); x is float [n_series][F * 1024], time order.
- * n_frames in [16, 2^24].  All calls are asynchronous on hip_stream.       */
+ * n_frames in [16, 2^19] (the kernels address one series with 32-bit
+ * offsets).  All calls are asynchronous on hip_stream.                     */
 
 /* y = H x (the analysis filterbank; also a station-PPF simulator).        */
 lp_status lp_ppf_analyze(lp_ctx *ctx, const lp_band *band, const float *x,
@@ -341,7 +342,8 @@ lp_status lp_sim_adc(lp_ctx *ctx, const lp_sim_cfg *cfg, int64_t n0,
  * before them: [n_in][(n_frames + 15) * 1024] int16), times scale, rounded
  * half to even and saturated to the int8 or int16 range (dtype LP_CI8 or
  * LP_CI16), written as the beamformer's input x [n_sb][n_frames][n_in]
- * complex.  n_in <= 128.  work: device, >= lp_station_work_bytes().        */
+ * complex.  n_in <= 128, n_frames <= 2^19 - 30.  work: device, >=
+ * lp_station_work_bytes().                                                  */
 size_t lp_station_work_bytes(int32_t n_in, int32_t n_sb, int64_t n_frames);
 lp_status lp_station_ppf(lp_ctx *ctx, const lp_band *band, const int16_t *adc,
                          int32_t n_in, int64_t n_frames, float scale,

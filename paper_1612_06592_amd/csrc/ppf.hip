@@ -40,6 +40,10 @@ constexpr int kPpfWg = 256;        // frames per workgroup
 constexpr int kPpfChunk = 32;      // real frames per chunk
 constexpr int kPpfNormParts = 2048; // partial sums of ||y||^2 per series
 constexpr int kPpfStateBytes = 128;
+// Frames per series of the operators: with nf <= 2^19 every byte offset
+// into one series' arrays (and into its n_sb <= 511 rows of nf complex
+// frames, chunk overrun included) stays below 2^31.
+constexpr long kPpfMaxFrames = 1L << 19;
 
 enum { kFwdAnalyze = 0, kFwdLsmr = 1, kFwdResid = 2, kFwdStation = 3 };
 enum { kAdjPlain = 0, kAdjLsmr = 1 };
@@ -184,16 +188,35 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_fwd_kernel(
   const long F = nf - (kTaps - 1);
   const long N = F * kM;
   const int tid = threadIdx.x;
-  const int f = tid & 15, j = tid >> 4;  // transform layout
-  const float *xs = static_cast<const float *>(xin_) + (long)series * N;
-  const short *xq = static_cast<const short *>(xin_) + (long)series * N;
-  auto ld = [&](long idx) -> float {
-    return MODE == kFwdStation ? (float)xq[idx] : xs[idx];
+  // Raw buffer views of this series' arrays, addressed by 32-bit byte
+  // offsets (nf <= 2^19 keeps every offset below 2^31): a load past a
+  // view's end, or at a negative offset (which wraps above 2^31), reads
+  // zero and a store there is dropped - the zero frames before and after
+  // the series.
+  constexpr int xes = MODE == kFwdStation ? 2 : 4;  // input element bytes
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<char *>(static_cast<const char *>(xin_)) + (long)series * N * xes,
+      0, (int)(N * xes), kRawBufferWord3);
+  auto ldx = [&](int e) -> float {  // input element e of the series
+    if constexpr (MODE == kFwdStation)
+      return (float)(short)__builtin_amdgcn_raw_buffer_load_b16(
+          rx, (unsigned)e * xes, 0, 0);
+    else
+      return __uint_as_float(
+          __builtin_amdgcn_raw_buffer_load_b32(rx, (unsigned)e * xes, 0, 0));
   };
+  auto view = [&](float *a) {
+    return __builtin_amdgcn_make_buffer_rsrc(a + (long)series * N, 0,
+                                             (int)(N * 4), kRawBufferWord3);
+  };
+  const __amdgpu_buffer_rsrc_t rh = view(hv), rhb = view(hbar), rxv = view(xv);
   const long nout = nf - 2 * (kTaps - 1);  // station mode: valid frames
-  const long vbase = (long)series * N;
-  const float2 *yi = yin + (long)series * n_sb * nf;
-  float2 *yo = yout + (long)series * n_sb * nf;
+  const int ybytes = (int)((long)n_sb * nf * 8);
+  const __amdgpu_buffer_rsrc_t ryi = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float2 *>(yin) + (long)series * n_sb * nf, 0, ybytes,
+      kRawBufferWord3);
+  const __amdgpu_buffer_rsrc_t ryo = __builtin_amdgcn_make_buffer_rsrc(
+      yout + (long)series * n_sb * nf, 0, ybytes, kRawBufferWord3);
   fill_tw_tables(tw, tw_p1, tw_p2);  // used after the first FIR barrier
   // Taps are g = 1024 h: fold 1 / 1024 into the input scale (exact).
   float ps = 1.f, qs = 0.f, c_hbar = 0.f, c_x = 0.f, c_h = 0.f;
@@ -213,10 +236,8 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_fwd_kernel(
   float ring[16];
   ring[0] = 0.f;
 #pragma unroll
-  for (int i = 1; i < 16; ++i) {
-    const long m = m0 - 16 + i;
-    ring[i] = (m >= 0 && m < F) ? ld(m * kM + (kM - 1 - tid)) * sc : 0.f;
-  }
+  for (int i = 1; i < 16; ++i)  // frames m0 - 15 .. m0 - 1 (zero if < 0)
+    ring[i] = ldx((int)(m0 - 16 + i) * kM + (kM - 1 - tid)) * sc;
   float acc = 0.f;
   for (int c = 0; c < kPpfWg / kPpfChunk; ++c) {
     const long mc = m0 + (long)c * kPpfChunk;
@@ -228,36 +249,43 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_fwd_kernel(
     for (int t = 0; t < 16; ++t) g[t] = taps[t * kM + ro];
     __syncthreads();  // the previous chunk's reads of lds are done
     // ---- FIR of column r over the chunk's 32 frames, packed in pairs.
+    // Element e0 + 1024 i is frame mc + i of column r (zero for frames
+    // >= F: past the view).
+    const int e0 = (int)mc * kM + (kM - 1 - ro);
     float prev = 0.f;
 #pragma unroll
     for (int g8 = 0; g8 < 4; ++g8) {
       float pv[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const long m = mc + 8 * g8 + i;
-        pv[i] = (m < F) ? ld(m * kM + (kM - 1 - ro)) : 0.f;
-      }
+      for (int i = 0; i < 8; ++i) pv[i] = ldx(e0 + (8 * g8 + i) * kM);
       if (MODE == kFwdLsmr) {
         // Pending update (hbar_k, x_k, h_{k+1}) on the unknowns this
-        // workgroup owns, with v_{k+1} = p p_scale.
+        // workgroup owns, with v_{k+1} = p p_scale (frames >= F: the
+        // stores fall past the views and are dropped).
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          const long m = mc + 8 * g8 + i;
-          if (m < F) {
-            const long idx = vbase + m * kM + (kM - 1 - ro);
-            const float v = pv[i] * ps;
-            if (first) {
-              hv[idx] = v;
-              hbar[idx] = 0.f;
-              xv[idx] = 0.f;
-            } else {
-              const float h0 = hv[idx];
-              const float hb = h0 - c_hbar * hbar[idx];
-              const float xn = xv[idx] + c_x * hb;
-              hbar[idx] = hb;
-              xv[idx] = xn;
-              hv[idx] = v - c_h * h0;
-            }
+          const unsigned o = (unsigned)(e0 + (8 * g8 + i) * kM) * 4u;
+          const float v = pv[i] * ps;
+          if (first) {
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rh, o,
+                                                  0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(0u, rhb, o, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(0u, rxv, o, 0, 0);
+          } else {
+            const float h0 = __uint_as_float(
+                __builtin_amdgcn_raw_buffer_load_b32(rh, o, 0, 0));
+            const float hb =
+                h0 - c_hbar * __uint_as_float(
+                                  __builtin_amdgcn_raw_buffer_load_b32(rhb, o, 0, 0));
+            const float xn =
+                __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rxv, o, 0, 0)) +
+                c_x * hb;
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(hb), rhb, o,
+                                                  0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(xn), rxv, o,
+                                                  0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(
+                __float_as_uint(v - c_h * h0), rh, o, 0, 0);
           }
         }
       }
@@ -290,12 +318,22 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_fwd_kernel(
       val[0] = make_float2(0.5f * (C.x + D.x), 0.5f * (C.y - D.y));
       val[1] = make_float2(0.5f * (C.y + D.y), -0.5f * (C.x - D.x));
       const long m = mc + 2 * pi;
-      const long o = (long)s * nf + m;
+      const unsigned ob = (unsigned)((int)s * (int)nf + (int)m) * 8u;
+      auto ystore = [&](unsigned off, float2 w) {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        u2 b = {__float_as_uint(w.x), __float_as_uint(w.y)};
+        __builtin_amdgcn_raw_buffer_store_b64(b, ryo, off, 0, 0);
+      };
+      auto yload = [&](unsigned off) -> float2 {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        const u2 b = __builtin_amdgcn_raw_buffer_load_b64(ryi, off, 0, 0);
+        return make_float2(__uint_as_float(b[0]), __uint_as_float(b[1]));
+      };
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         if (m + e < nf) {
           if (MODE == kFwdAnalyze) {
-            yo[o + e] = val[e];
+            ystore(ob + 8 * e, val[e]);
           } else if (MODE == kFwdStation) {
             const long mo = m + e - (kTaps - 1);
             if (mo >= 0 && mo < nout) {
@@ -308,13 +346,13 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_fwd_kernel(
                   make_short2((short)re, (short)im);
             }
           } else if (MODE == kFwdLsmr) {
-            const float2 q0 = yi[o + e];
+            const float2 q0 = yload(ob + 8 * e);
             const float2 qn = make_float2(val[e].x - qs * q0.x,
                                           val[e].y - qs * q0.y);
-            yo[o + e] = qn;
+            ystore(ob + 8 * e, qn);
             acc = fmaf(qn.x, qn.x, fmaf(qn.y, qn.y, acc));
           } else {
-            const float2 y0 = yi[o + e];
+            const float2 y0 = yload(ob + 8 * e);
             const float rx = y0.x - val[e].x, ry = y0.y - val[e].y;
             acc = fmaf(rx, rx, fmaf(ry, ry, acc));
           }
@@ -675,8 +713,9 @@ static lp_status ppf_check(const char *who, lp_ctx *ctx, const lp_band *band,
   if (rc) return rc;
   if (n_series <= 0 || n_series > 65535)
     return set_error(LP_EINVAL, "%s: n_series %d", who, n_series);
-  if (nf < kTaps || nf > (1L << 24))
-    return set_error(LP_EINVAL, "%s: n_frames %ld outside [%d, 2^24]", who,
+  // The operators address one series with 32-bit byte offsets.
+  if (nf < kTaps || nf > kPpfMaxFrames)
+    return set_error(LP_EINVAL, "%s: n_frames %ld outside [%d, 2^19]", who,
                      nf, kTaps);
   return LP_OK;
 }
@@ -837,9 +876,9 @@ extern "C" lp_status lp_station_ppf(lp_ctx *ctx, const lp_band *band,
   if (rc) return rc;
   if (n_in < 1 || n_in > 128)
     return set_error(LP_EINVAL, "lp_station_ppf: n_in %d not in 1..128", n_in);
-  if (n_frames < 1 || n_frames > (1L << 24))
-    return set_error(LP_EINVAL, "lp_station_ppf: n_frames %lld",
-                     (long long)n_frames);
+  if (n_frames < 1 || n_frames > kPpfMaxFrames - 2 * (kTaps - 1))
+    return set_error(LP_EINVAL, "lp_station_ppf: n_frames %lld outside "
+                     "[1, 2^19 - 30]", (long long)n_frames);
   if (!(scale > 0.f) || !std::isfinite(scale))
     return set_error(LP_EINVAL, "lp_station_ppf: scale must be positive");
   if (dtype != LP_CI8 && dtype != LP_CI16)

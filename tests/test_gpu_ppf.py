@@ -172,6 +172,14 @@ def test_invert_edge_cases():
         lp.ppf_invert(ctx, band, yd, 1, nf, 5, x, w[:-256])   # short work
     with pytest.raises(lp.LpError):
         lp.ppf_invert(ctx, band, yd, 1, nf, -1, x, w)         # n_iter < 0
+    # Beyond 2^19 frames the operators' 32-bit offsets do not reach.
+    with pytest.raises(lp.LpError, match="2\\^19"):
+        lp.ppf_invert(ctx, band, yd, 1, (1 << 19) + 1, 5, x, w)
+    with pytest.raises(lp.LpError, match="2\\^19"):
+        lp.ppf_analyze(ctx, band, x, 1, (1 << 19) + 1, yd)
+    adc = torch.zeros(16 * M, dtype=torch.int16, device="cuda:0")
+    with pytest.raises(lp.LpError, match="2\\^19"):
+        lp.station_ppf(ctx, band, adc, 1, (1 << 19) - 29, 1.0, w, w)
     ctx.close()
 
 
