@@ -375,6 +375,10 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_adj_kernel(
   __shared__ float2 lds[16 * kPpfFs];
   __shared__ float2 tw_p1[kTwP1], tw_p2[kTwP2];
   __shared__ float red[16];
+  // Element offset si nf in y of the subband feeding bin j + 64 q of the
+  // packed spectrum (q < 8: bin k = j + 64 q; q >= 8: its mirror 1024 - k),
+  // or -1: [q][j].
+  __shared__ int soff[16 * 64];
 
   const int series = blockIdx.y;
   const long F = nf - (kTaps - 1);
@@ -387,6 +391,16 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_adj_kernel(
   const float2 *yi = yin + (long)series * n_sb * nf;
   float *po = pio + (long)series * N;
   fill_tw_tables(tw, tw_p1, tw_p2);  // used after the first pass-0 barrier
+  {
+    const int q = tid >> 6, b = (tid & 63) + 64 * q;
+    const int si = q < 8 ? binmap[b] : (b == 512 ? -1 : binmap[kM - b]);
+    soff[tid] = si >= 0 ? si * (int)nf : -1;
+  }
+  // The series' p through a raw buffer view (32-bit offsets; nf <= 2^19).
+  const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc(
+      po, 0, (int)(N * 4), kRawBufferWord3);
+  const char *yb = reinterpret_cast<const char *>(yi);
+  __syncthreads();
   // Packing halves, taps g = 1024 h: both folded into the input scale.
   float is = 0.5f / 1024.f, vs = 0.f;
   if (MODE == kAdjLsmr) {
@@ -407,20 +421,17 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_adj_kernel(
     // u_odd) / 2; zero elsewhere.  Pass 0 reads bins jo + 64 q.
     float2 v[16];
     {
-      const long m = mc + 2 * fo;
+      const int m = (int)mc + 2 * fo;
+      const bool in0 = m < (int)nf, in1 = m + 1 < (int)nf;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        const int b = jo + 64 * q;
-        int si;
-        if (q < 8)
-          si = binmap[b];
-        else
-          si = (b == 512) ? -1 : binmap[kM - b];
+        const int o = soff[64 * q + jo];
         float2 a = make_float2(0.f, 0.f), bb = make_float2(0.f, 0.f);
-        if (si >= 0) {
-          const float2 *row = yi + (long)si * nf;
-          if (m < nf) a = row[m];
-          if (m + 1 < nf) bb = row[m + 1];
+        if (o >= 0) {
+          // 32-bit byte offsets from the series base (n_sb nf 8 < 2^31).
+          const unsigned ob = (unsigned)(o + m) * 8u;
+          if (in0) a = *reinterpret_cast<const float2 *>(yb + ob);
+          if (in1) bb = *reinterpret_cast<const float2 *>(yb + ob + 8);
         }
         v[q] = (q < 8) ? make_float2((a.x - bb.y) * is, (a.y + bb.x) * is)
                        : make_float2((a.x + bb.y) * is, (bb.x - a.y) * is);
@@ -449,7 +460,8 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_adj_kernel(
         const long jj = mc + 8 * g8 + i - (kTaps - 1);
         pold[i] = 0.f;
         if (MODE == kAdjLsmr && vs != 0.f && jj >= j0 && jj < jend)
-          pold[i] = po[jj * kM + (kM - 1 - ro)];
+          pold[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+              rp, (unsigned)((int)jj * kM + (kM - 1 - ro)) * 4u, 0, 0));
       }
       float2 w2 = make_float2(0.f, 0.f);
 #pragma unroll
@@ -467,7 +479,9 @@ __global__ __launch_bounds__(kPpfThreads) void ppf_adj_kernel(
             a = fmaf(-vs, pold[i], a);
             acc = fmaf(a, a, acc);
           }
-          po[jj * kM + (kM - 1 - ro)] = a;
+          __builtin_amdgcn_raw_buffer_store_b32(
+              __float_as_uint(a), rp,
+              (unsigned)((int)jj * kM + (kM - 1 - ro)) * 4u, 0, 0);
         }
       }
     }
