@@ -183,6 +183,30 @@ def test_invert_edge_cases():
     ctx.close()
 
 
+def test_operators_and_solve_bitwise_repeatable():
+    """H, H^T and an LSMR solve run twice on the same inputs give the same
+    bits (fixed-order reductions, no races in the wave-local transforms)."""
+    ns, nf = 2, 600
+    F = nf - P + 1
+    rng = np.random.default_rng(21)
+    k = np.arange(40, 120)
+    band = lp.Band(k)
+    ctx = lp.Ctx(0)
+    x = rng.standard_normal((ns, F * M))
+    y = rng.standard_normal((ns, len(k), nf)) + 1j * rng.standard_normal((ns, len(k), nf))
+    print("case ppf repeatability ns=2 nf=600", flush=True)
+    a1, a2 = _analyze(ctx, band, x, ns, nf), _analyze(ctx, band, x, ns, nf)
+    assert np.array_equal(a1, a2)
+    b1, b2 = _adjoint(ctx, band, y, ns, nf), _adjoint(ctx, band, y, ns, nf)
+    assert np.array_equal(b1, b2)
+    yd = _to_dev_c(y)
+    x1, an1, rn1 = _invert(ctx, band, yd, ns, nf, 10)
+    x2, an2, rn2 = _invert(ctx, band, yd, ns, nf, 10)
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+    assert np.array_equal(an1, an2) and np.array_equal(rn1, rn2)
+    ctx.close()
+
+
 def test_full_size_c2_band():
     """C2's band and block length (244 subbands, 65536 frames), one series."""
     import torch
