@@ -15,7 +15,9 @@
 // Kernels.  Both operators stream 256 frames per 1024-thread workgroup in
 // chunks of 32 real frames, packed two per complex 1024-point transform
 // (16 transforms per chunk in a 139 KB LDS tile, Stockham radix 16, 16,
-// 4).  Thread r owns FIR column r and keeps 16 frames of it in registers.
+// 4, wave w transforming packed frame w).  Thread r owns FIR column r and
+// keeps 16 frames of it in registers.  A series' arrays are addressed with
+// 32-bit offsets (n_frames <= 2^19).
 //   ppf_fwd_kernel: FIR (16 FMA per sample) -> packed transform -> the
 //     recorded bins of both frames from bins k and 1024 - k.  In LSMR mode
 //     it also forms u = H v - (alpha / beta) u_old with its squared-norm

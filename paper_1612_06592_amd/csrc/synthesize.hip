@@ -10,7 +10,9 @@
 //
 // One 1024-thread workgroup per (series, block of F frames).  Frames are
 // transformed 16 at a time in a 139 KB LDS tile (radix 16, 16, 4 Stockham
-// passes, 64 threads per frame); thread n then owns FIR column n and keeps
+// passes, 64 threads per frame: pass 0 in the fetch layout, passes 1 and 2
+// by one wave per frame, with no workgroup barrier between them); thread
+// n then owns FIR column n and keeps
 // Z_{m-15..m}[n] and its 16 taps in registers, so each output sample costs
 // 16 complex-by-real FMAs and nothing is written to HBM except the
 // per-frame envelope maximum (+ arg), per-16-frame sums of (2 Re z)^2 and,
