@@ -222,6 +222,10 @@ lp_status lp_ctx_create(int32_t hip_device, lp_ctx **out) {
   auto ctx = std::make_unique<lp_ctx>();
   ctx->device = hip_device;
   LP_HIP(hipSetDevice(hip_device));
+  LP_HIP(hipDeviceGetAttribute(&ctx->n_cu,
+                               hipDeviceAttributeMultiprocessorCount,
+                               hip_device));
+  if (ctx->n_cu <= 0) ctx->n_cu = 1;
   std::vector<float2> tw(4096);
   for (int i = 0; i < 4096; ++i) {
     double a = -2.0 * M_PI * i / 4096.0;

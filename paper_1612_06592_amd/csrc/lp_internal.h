@@ -88,6 +88,7 @@ struct TsPlan {
 
 struct lp_ctx {
   int device = 0;
+  int n_cu = 256;     // compute units of the device
   lp::DevBuf tw4096;  // float2 exp(-2 pi i n / 4096), n < 4096
   std::mutex mu;
   std::vector<std::unique_ptr<lp::BfPlan>> bf;

@@ -314,10 +314,23 @@ lp_status syn_launch(lp_ctx *ctx, const SynPlan *p, int n_sb, const void *d,
   if ((long)n_sb * n_t * 8 >= (1L << 32))
     return set_error(LP_EINVAL, "synthesis: %d subbands x %ld frames too large",
                      n_sb, n_t);
-  // Frames per workgroup: long blocks amortise the 16-frame warm-up; short
-  // ones keep enough workgroups to fill the chip.
-  int F = 256;
-  while (F > 128 && (long)n_series * (n_t / F) < 256) F /= 2;
+  // Frames per workgroup F: each workgroup transforms a 16-frame warm-up
+  // chunk besides its F frames, and one workgroup fills a CU, so F / (F +
+  // 16) times the occupancy of the last round of workgroups over the CUs is
+  // the efficiency; take the best F (the longest on ties).  n_t is a
+  // multiple of 2048, so every candidate divides it.
+  int F = 128;
+  double best = -1.0;
+  for (int f : {1024, 512, 256, 128}) {
+    const long nw = (long)n_series * (n_t / f);
+    const long rounds = (nw + ctx->n_cu - 1) / ctx->n_cu;
+    const double eff =
+        (double)f / (f + 16) * (double)nw / ((double)rounds * ctx->n_cu);
+    if (eff > best + 1e-12) {
+      best = eff;
+      F = f;
+    }
+  }
   const long n_wg = n_t / F;
   char *cb = static_cast<char *>(cand);
   SynCand *cd = reinterpret_cast<SynCand *>(cb);
