@@ -19,6 +19,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -524,12 +525,42 @@ def run_cpu_baseline(blk, hops: int):
     st.process(xs)
     dt = time.perf_counter() - t0
     samples = cfg.n_in * cfg.n_sb * n * cfg.n_beams
-    return {"value": round(samples / dt / 1e6, 3), "unit": "Msamples/s",
-            "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"first {n} of {blk.n_t} samples per subband "
-                      f"(all {cfg.n_sb} subbands, {cfg.n_in} inputs, "
-                      f"{cfg.n_beams} beams, {cfg.n_tec} trials)",
-            "seconds": round(dt, 2)}
+    out = {"value": round(samples / dt / 1e6, 3), "unit": "Msamples/s",
+           "cores": oracle.threads(), "kind": "oracle",
+           "sample": f"first {n} of {blk.n_t} samples per subband "
+                     f"(all {cfg.n_sb} subbands, {cfg.n_in} inputs, "
+                     f"{cfg.n_beams} beams, {cfg.n_tec} trials)",
+           "seconds": round(dt, 2), "cpu_model": cpu_model(),
+           "nproc": os.cpu_count()}
+    # The same chain on one thread, over its first hop only (a fresh
+    # stream, so the same arithmetic as the first hop above).
+    n1 = min(2048, n)
+    cores = oracle.threads()
+    oracle.set_threads(1)
+    try:
+        st1 = oracle.Stream(blk.enu, 2, blk.k, blk.az_el, blk.tec)
+        t0 = time.perf_counter()
+        st1.process(blk.x[:, :n1])
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    out["single_thread"] = {
+        "value": round(cfg.n_in * cfg.n_sb * n1 * cfg.n_beams / dt1 / 1e6, 3),
+        "unit": "Msamples/s", "sample": f"first {n1} samples per subband",
+        "seconds": round(dt1, 2)}
+    return out
+
+
+def cpu_model() -> str:
+    """The host CPU's model name, as the kernel reports it."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
 def serving_bench(a):

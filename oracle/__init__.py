@@ -54,6 +54,7 @@ def lib():
         L.lpo_kappa.restype = C.c_double
         L.lpo_speed_of_light.restype = C.c_double
         L.lpo_threads.restype = C.c_int
+        L.lpo_set_threads.argtypes = [C.c_int]
         L.lpo_fft.argtypes = [lp, dp, C.c_int]
         L.lpo_bessel_i0.restype = C.c_double
         L.lpo_bessel_i0.argtypes = [C.c_double]
@@ -105,6 +106,11 @@ def speed_of_light() -> float:
 
 def threads() -> int:
     return lib().lpo_threads()
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's later parallel loops."""
+    lib().lpo_set_threads(int(n))
 
 
 def fft(x, inverse: bool = False) -> np.ndarray:

@@ -36,6 +36,9 @@ double lpo_kappa(void) {
 
 int lpo_threads(void) { return omp_get_max_threads(); }
 
+/* Thread count of later parallel loops (timing on one or more cores). */
+void lpo_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
 /* ------------------------------------------------------------------ FFT */
 
 void lpo_fft(long n, double complex *x, int inverse) {

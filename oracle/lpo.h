@@ -42,6 +42,7 @@ double lpo_speed_of_light(void);
 
 /* Number of OpenMP threads the oracle uses. */
 int lpo_threads(void);
+void lpo_set_threads(int n);
 
 /* In-place radix-2 FFT of length n (a power of two).
  * inverse = 0: X_q = sum_n x_n exp(-2 pi i q n / N)
