@@ -192,6 +192,9 @@ lp_status get_syn_plan(lp_ctx *ctx, const lp_band *band, SynPlan **out) {
   LP_HIP(hipMalloc(&p->taps.p, L * 4));
   LP_HIP(hipMalloc(&p->binmap.p, 512 * 2));
   LP_HIP(hipMemcpy(p->taps.p, g32.data(), L * 4, hipMemcpyHostToDevice));
+  for (int l = 0; l < L; ++l) g32[l] *= 2.f;
+  LP_HIP(hipMalloc(&p->taps2.p, L * 4));
+  LP_HIP(hipMemcpy(p->taps2.p, g32.data(), L * 4, hipMemcpyHostToDevice));
   LP_HIP(hipMemcpy(p->binmap.p, bm.data(), 512 * 2, hipMemcpyHostToDevice));
   std::vector<int16_t> kb(band->n_sb);
   for (int i = 0; i < band->n_sb; ++i) kb[i] = (int16_t)band->k[i];

@@ -70,6 +70,7 @@ struct DdPlan {
 struct SynPlan {
   std::vector<uint8_t> key;
   DevBuf taps;    // f32 [16][1024] g = M h
+  DevBuf taps2;   // f32 [16][1024] 2 g (synthesis of 2 z)
   DevBuf binmap;  // i16 [512] subband position of bin k, or -1
   DevBuf kbin;    // i16 [n_sb] bin k of each subband position
 };

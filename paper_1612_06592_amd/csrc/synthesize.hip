@@ -6,7 +6,8 @@
 //   Z_m[n] = sum_k d_k[m] exp(+2 pi i k n / 1024)        (1024-point IFFT)
 //   z[1024 m + n] = sum_{t<16} g[1024 t + n] Z_{m-t}[n]   (polyphase FIR)
 // with g = M h.  Only positive bins are filled, so z is analytic: the real
-// series is 2 Re z and the envelope |2 z|.
+// series is 2 Re z and the envelope |2 z|.  The kernel takes the taps as
+// 2 g, so its sums are 2 z directly (scaling by 2 is exact).
 //
 // One 1024-thread workgroup per (series, block of F frames).  Frames are
 // transformed 16 at a time in a 139 KB LDS tile (radix 16, 16, 4 Stockham
@@ -33,6 +34,65 @@ struct SynCand {
   int arg;
 };
 
+// Wavefront reductions by DPP lane exchanges (no LDS, no address
+// arithmetic).  Steps: quad lanes 1 and 2 apart, then the mirrors of each
+// 8 and 16 lanes, after which every lane holds its 16-lane row's result;
+// then lane 15 of rows 0 and 2 into rows 1 and 3, and lane 31 into rows 2
+// and 3, so lane 63 holds the wavefront's result.
+constexpr int kDppQuadX1 = 0xB1, kDppQuadX2 = 0x4E, kDppHalfMirror = 0x141,
+              kDppMirror = 0x140, kDppBcast15 = 0x142, kDppBcast31 = 0x143;
+
+// Lane exchange CTRL in the rows of ROWS; lanes of the other rows get
+// `old`.  (Every exchange here reads lanes inside the wavefront.)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i(int v, int old) {
+  if constexpr (ROWS == 0xF)
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+  else
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xF, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f(float v, float old) {
+  return __int_as_float(dpp_i<CTRL, ROWS>(__float_as_int(v), __float_as_int(old)));
+}
+
+// Sum over the wavefront, valid in lane 63.
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v += dpp_f<kDppQuadX1, 0xF>(v, 0.f);
+  v += dpp_f<kDppQuadX2, 0xF>(v, 0.f);
+  v += dpp_f<kDppHalfMirror, 0xF>(v, 0.f);
+  v += dpp_f<kDppMirror, 0xF>(v, 0.f);
+  v += dpp_f<kDppBcast15, 0xA>(v, 0.f);
+  v += dpp_f<kDppBcast31, 0xC>(v, 0.f);
+  return v;
+}
+
+// One step of the (largest value, lowest index) reduction; lanes of rows
+// outside ROWS compare with themselves and keep their pair.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void argmax_step(float &bv, int &bi) {
+  const float ov = dpp_f<CTRL, ROWS>(bv, bv);
+  const int oi = dpp_i<CTRL, ROWS>(bi, bi);
+  const bool take = (ov > bv) | ((ov == bv) & (oi < bi));
+  bv = take ? ov : bv;
+  bi = take ? oi : bi;
+}
+
+// Largest value and its lowest index over the wavefront, valid in lane 63.
+__device__ __forceinline__ void wave_argmax_dpp(float &bv, int &bi) {
+  argmax_step<kDppQuadX1, 0xF>(bv, bi);
+  argmax_step<kDppQuadX2, 0xF>(bv, bi);
+  argmax_step<kDppHalfMirror, 0xF>(bv, bi);
+  argmax_step<kDppMirror, 0xF>(bv, bi);
+  argmax_step<kDppBcast15, 0xA>(bv, bi);
+  argmax_step<kDppBcast31, 0xC>(bv, bi);
+}
+
+// MASKED: some chunk straddles the end of the warm-up (`warm` - frame0 not
+// a multiple of 16), so the statistics mask frame by frame; otherwise a
+// chunk is either all warm-up or all valid.
+template <bool MASKED>
 __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     const float2 *__restrict__ d, float2 *__restrict__ hist,
     const short *__restrict__ binmap, const float *__restrict__ taps,
@@ -199,7 +259,7 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
       for (int fi = 0; fi < 16; ++fi) win[fi] = lds[fi * kSynFs + pad16(no)];
       continue;
     }
-    // Taps are reloaded per chunk (cache hits) so they do not occupy
+    // Taps (2 g) are reloaded per chunk (cache hits) so they do not occupy
     // registers during the transform.
     // A raw buffer view of the 16 x 1024 taps: tap t of column n is at the
     // constant offset 4096 t plus 4 n, so the loads need no address
@@ -216,6 +276,8 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     const long fv = warm - (frame0 + mc);
     const int first_valid = fv <= 0 ? 0 : (fv >= 16 ? 16 : (int)fv);
     float *xo = x_out ? x_out + ((long)series * n_t + mc) * 1024 + no : nullptr;
+    // (zr, zi) = 2 z of frame fi: 2 Re z is the real series, |2 z|^2 the
+    // squared envelope; the slot is consumed, so it takes the latter.
 #pragma unroll
     for (int fi = 0; fi < 16; ++fi) {
       float2 *slot = lds + fi * kSynFs + pad16(no);
@@ -227,15 +289,13 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
         zr = fmaf(g[t], w.x, zr);
         zi = fmaf(g[t], w.y, zi);
       }
-      const float xr = 2.f * zr;
-      if (fi >= first_valid) acc_s = fmaf(xr, xr, acc_s);
-      if (xo) xo[(long)fi * 1024] = xr;
-      // The slot is consumed: reuse it for the squared envelope.
-      slot->x = 4.f * (zr * zr + zi * zi);
+      if (!MASKED || fi >= first_valid) acc_s = fmaf(zr, zr, acc_s);
+      if (xo) xo[(long)fi * 1024] = zr;
+      slot->x = zr * zr + zi * zi;
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) acc_s += __shfl_xor(acc_s, off);
-    if (lo == 0) red_s[wo] = acc_s;
+    if (!MASKED && first_valid != 0) acc_s = 0.f;  // first_valid is 16
+    acc_s = wave_sum_dpp(acc_s);
+    if (lo == 63) red_s[wo] = acc_s;
     __syncthreads();
     // Wave w finds the envelope maximum of frame w (lowest n on ties).
     {
@@ -254,16 +314,8 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
         }
       }
       int bi = lo + 64 * bk;
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        float ov = __shfl_xor(bv, off);
-        int oi = __shfl_xor(bi, off);
-        if (ov > bv || (ov == bv && oi < bi)) {
-          bv = ov;
-          bi = oi;
-        }
-      }
-      if (lo == 0) {
+      wave_argmax_dpp(bv, bi);
+      if (lo == 63) {
         SynCand o;
         o.emax = sqrtf(bv);
         o.arg = bi;
@@ -332,15 +384,18 @@ lp_status syn_launch(lp_ctx *ctx, const SynPlan *p, int n_sb, const void *d,
     }
   }
   const long n_wg = n_t / F;
+  const long warm = kDelay + kTaps;
+  const bool masked = frame0 < warm && (warm - frame0) % 16 != 0;
   char *cb = static_cast<char *>(cand);
   SynCand *cd = reinterpret_cast<SynCand *>(cb);
   float *ps = reinterpret_cast<float *>(cb + (size_t)n_series * cand_nt * 8);
-  hipLaunchKernelGGL(syn_kernel, dim3((unsigned)n_wg, n_series),
+  auto *kern = masked ? syn_kernel<true> : syn_kernel<false>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)n_wg, n_series),
                      dim3(kSynThreads), 0, st, static_cast<const float2 *>(d),
                      static_cast<float2 *>(hist), p->binmap.as<const short>(),
-                     p->taps.as<const float>(), ctx->tw4096.as<const float2>(),
-                     x_out, cd, ps, n_sb, n_t, frame0,
-                     (long)(kDelay + kTaps), F, cand_nt, cand_t0);
+                     p->taps2.as<const float>(), ctx->tw4096.as<const float2>(),
+                     x_out, cd, ps, n_sb, n_t, frame0, warm, F, cand_nt,
+                     cand_t0);
   LP_HIP(hipGetLastError());
   return LP_OK;
 }

@@ -229,6 +229,59 @@ def test_determinism_bitwise():
     assert np.array_equal(a["trig"], b["trig"])
 
 
+@pytest.mark.parametrize("frame0", [0, 8, 16, 1000, 1037, 1040, 4096])
+def test_synthesis_warmup_statistics(frame0):
+    """Variance sums exclude exactly the warm-up frames (stream time below
+    WARM) also where that boundary falls inside a 16-frame chunk (stream
+    positions that are not multiples of 16); window maxima do not depend
+    on the position.  Against the oracle's synthesis and detection on the
+    same FP32 subband samples."""
+    import torch
+
+    import oracle
+    rng = np.random.default_rng(1612 + frame0)
+    k = np.arange(52, 84)
+    S, n_t, ns = len(k), 2048, 2
+    d = (rng.standard_normal((ns, S, n_t))
+         + 1j * rng.standard_normal((ns, S, n_t))).astype(np.complex64)
+    ctx = lp.Ctx(0)
+    band = lp.Band(k)
+    dd = torch.from_numpy(d.view(np.float32).reshape(ns, S, n_t, 2)).to("cuda:0")
+    hist = torch.zeros(ns * S * 16 * 2, dtype=torch.float32, device="cuda:0")
+    cand = torch.empty(lp.nbytes("lp_cand_bytes", ns, n_t), dtype=torch.uint8,
+                       device="cuda:0")
+    print(f"synthesis warm-up statistics, frame0 {frame0}", flush=True)
+    lp.synthesize(ctx, band, dd, ns, n_t, frame0, hist, cand)
+    torch.cuda.synchronize()
+    cb = cand.cpu().numpy()
+    c = cb[:ns * n_t * 8].view(np.float32).reshape(ns, n_t, 2)
+    emax, arg = c[..., 0], c[..., 1].view(np.int32)
+    psum = cb[ns * n_t * 8:ns * n_t * 8 + ns * (n_t // 16) * 4].view(
+        np.float32).reshape(ns, n_t // 16)
+    ctx.close()
+    h = oracle.prototype()
+    z = oracle.synthesize(h, k, d.astype(np.complex128),
+                          np.zeros((ns, 15, S), np.complex128))
+    sigma, wmax, warg = oracle.detect(z, n_t, frame0, WARM)
+    n_valid = int(np.sum(frame0 + np.arange(n_t) >= WARM))
+    if n_valid:
+        gs = np.sqrt(psum.astype(np.float64).sum(1) / (n_valid * 1024))
+        assert np.max(np.abs(gs - sigma) / sigma) <= 1e-5, (gs, sigma)
+    else:
+        assert not np.any(psum)
+    # Chunks wholly inside the warm-up contribute nothing.
+    whole = (WARM - frame0) // 16
+    if whole > 0:
+        assert not np.any(psum[:, :min(whole, n_t // 16)])
+    assert rel_rms(emax, wmax) <= 1e-5
+    # Arg-max: the oracle's, or a sample whose envelope is within 1e-5 of
+    # the window maximum (a near tie).
+    env = np.abs(2 * z).reshape(ns, n_t, 1024)
+    for q in range(ns):
+        for m in np.nonzero(arg[q] != warg[q] % 1024)[0]:
+            assert env[q, m, arg[q, m]] >= (1 - 1e-5) * wmax[q, m], (q, m)
+
+
 @pytest.mark.parametrize("case", ["c1", "c2s"])
 def test_plain_fp32_comparator(case):
     """The plain comparator pipeline matches the oracle at FP32 accuracy
