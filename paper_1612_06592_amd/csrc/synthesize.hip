@@ -68,25 +68,16 @@ __device__ __forceinline__ float wave_sum_dpp(float v) {
   return v;
 }
 
-// One step of the (largest value, lowest index) reduction; lanes of rows
-// outside ROWS compare with themselves and keep their pair.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ void argmax_step(float &bv, int &bi) {
-  const float ov = dpp_f<CTRL, ROWS>(bv, bv);
-  const int oi = dpp_i<CTRL, ROWS>(bi, bi);
-  const bool take = (ov > bv) | ((ov == bv) & (oi < bi));
-  bv = take ? ov : bv;
-  bi = take ? oi : bi;
-}
-
-// Largest value and its lowest index over the wavefront, valid in lane 63.
-__device__ __forceinline__ void wave_argmax_dpp(float &bv, int &bi) {
-  argmax_step<kDppQuadX1, 0xF>(bv, bi);
-  argmax_step<kDppQuadX2, 0xF>(bv, bi);
-  argmax_step<kDppHalfMirror, 0xF>(bv, bi);
-  argmax_step<kDppMirror, 0xF>(bv, bi);
-  argmax_step<kDppBcast15, 0xA>(bv, bi);
-  argmax_step<kDppBcast31, 0xC>(bv, bi);
+// Unsigned maximum over the wavefront, returned to every lane (rows
+// outside the broadcast masks take the maximum with themselves).
+__device__ __forceinline__ unsigned wave_umax_dpp(unsigned v) {
+  v = max(v, (unsigned)dpp_i<kDppQuadX1, 0xF>((int)v, 0));
+  v = max(v, (unsigned)dpp_i<kDppQuadX2, 0xF>((int)v, 0));
+  v = max(v, (unsigned)dpp_i<kDppHalfMirror, 0xF>((int)v, 0));
+  v = max(v, (unsigned)dpp_i<kDppMirror, 0xF>((int)v, 0));
+  v = max(v, (unsigned)dpp_i<kDppBcast15, 0xA>((int)v, (int)v));
+  v = max(v, (unsigned)dpp_i<kDppBcast31, 0xC>((int)v, (int)v));
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 // MASKED: some chunk straddles the end of the warm-up (`warm` - frame0 not
@@ -297,27 +288,30 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     acc_s = wave_sum_dpp(acc_s);
     if (lo == 63) red_s[wo] = acc_s;
     __syncthreads();
-    // Wave w finds the envelope maximum of frame w (lowest n on ties).
+    // Wave w finds the envelope maximum of frame w and its lowest n: the
+    // maximum first, then per row n = 64 i + lane a ballot of the lanes
+    // holding it; the first row with a hit and its lowest lane give n.
+    // Squared envelopes are >= +0, so their bit patterns order as unsigned
+    // integers: the maximum is an exact selection.
     {
-      const float2 *fr = lds + wo * kSynFs;
-      // Lane l scans n = l + 64 i (slot pad16(n) = l + l / 16 + 68 i),
-      // keeping the first i of its maximum.
-      float bv = -1.f;
-      int bk = 0;
-      const float2 *fl = fr + lo + (lo >> 4);
+      // Lane l holds n = l + 64 i at slot pad16(n) = l + l / 16 + 68 i.
+      const float2 *fl = lds + wo * kSynFs + lo + (lo >> 4);
+      unsigned e2[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        float e2 = fl[68 * i].x;
-        if (e2 > bv) {
-          bv = e2;
-          bk = i;
-        }
+      for (int i = 0; i < 16; ++i) e2[i] = __float_as_uint(fl[68 * i].x);
+      unsigned bv = e2[0];
+#pragma unroll
+      for (int i = 1; i < 16; ++i) bv = max(bv, e2[i]);
+      bv = wave_umax_dpp(bv);
+      int bi = 0;
+#pragma unroll
+      for (int i = 15; i >= 0; --i) {
+        const unsigned long long hit = __builtin_amdgcn_ballot_w64(e2[i] == bv);
+        if (hit) bi = 64 * i + __builtin_ctzll(hit);
       }
-      int bi = lo + 64 * bk;
-      wave_argmax_dpp(bv, bi);
-      if (lo == 63) {
+      if (lo == 0) {
         SynCand o;
-        o.emax = sqrtf(bv);
+        o.emax = sqrtf(__uint_as_float(bv));
         o.arg = bi;
         cand[(long)series * cand_nt + cand_t0 + mc + wo] = o;
       }
