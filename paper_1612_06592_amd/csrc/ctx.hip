@@ -189,6 +189,8 @@ lp_status get_syn_plan(lp_ctx *ctx, const lp_band *band, SynPlan **out) {
   for (int l = 0; l < L; ++l) g32[l] = (float)(kM * h[l] / sum);
   std::vector<int16_t> bm(512, -1);
   for (int i = 0; i < band->n_sb; ++i) bm[band->k[i]] = (int16_t)i;
+  p->kmax = 0;
+  for (int i = 0; i < band->n_sb; ++i) p->kmax = std::max(p->kmax, (int)band->k[i]);
   LP_HIP(hipMalloc(&p->taps.p, L * 4));
   LP_HIP(hipMalloc(&p->binmap.p, 512 * 2));
   LP_HIP(hipMemcpy(p->taps.p, g32.data(), L * 4, hipMemcpyHostToDevice));

@@ -73,6 +73,7 @@ struct SynPlan {
   DevBuf taps2;   // f32 [16][1024] 2 g (synthesis of 2 z)
   DevBuf binmap;  // i16 [512] subband position of bin k, or -1
   DevBuf kbin;    // i16 [n_sb] bin k of each subband position
+  int kmax = 511;  // highest bin of the band
 };
 
 // Two-stage beamforming: stage-2 coefficients for one (array, grouping,

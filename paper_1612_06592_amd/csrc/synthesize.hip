@@ -82,8 +82,10 @@ __device__ __forceinline__ unsigned wave_umax_dpp(unsigned v) {
 
 // MASKED: some chunk straddles the end of the warm-up (`warm` - frame0 not
 // a multiple of 16), so the statistics mask frame by frame; otherwise a
-// chunk is either all warm-up or all valid.
-template <bool MASKED>
+// chunk is either all warm-up or all valid.  NR: bins j + 64 r with r >= NR
+// are empty in the band (its highest bin is below 64 NR), so the first
+// transform pass reads NR inputs and the rest are known zeros.
+template <bool MASKED, int NR>
 __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     const float2 *__restrict__ d, float2 *__restrict__ hist,
     const short *__restrict__ binmap, const float *__restrict__ taps,
@@ -141,9 +143,9 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
   __syncthreads();
 
   const int n_chunk = F / 16;
-  // Pass-0 inputs of a chunk: bins j + 64 r (r < 8; bins >= 512 are empty)
-  // of frame mc + f, from d or, before the block, from the history.
-  float2 pre[8];
+  // Pass-0 inputs of a chunk: bins j + 64 r (r < NR; bins >= 64 NR are
+  // empty) of frame mc + f, from d or, before the block, from the history.
+  float2 pre[NR];
   auto fetch = [&](long mc_) {
     const int jo = opaque(j), fo = opaque(f);
     if (mc_ >= 0) {
@@ -152,7 +154,7 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
       const int m = (int)mc_ + fo;
       const char *db = reinterpret_cast<const char *>(ds);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
+      for (int r = 0; r < NR; ++r) {
         const int o = soff[64 * r + jo];
         pre[r] = make_float2(0.f, 0.f);
         if (o >= 0)
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     } else {
       const long m = mc_ + fo;
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
+      for (int r = 0; r < NR; ++r) {
         int si = binmap[jo + 64 * r];
         pre[r] = make_float2(0.f, 0.f);
         if (si >= 0)
@@ -180,9 +182,9 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     // ---- pass 0 (radix 16, Ns = 1).
     float2 v[16];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) v[r] = pre[r];
+    for (int r = 0; r < NR; ++r) v[r] = pre[r];
 #pragma unroll
-    for (int r = 8; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
+    for (int r = NR; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
     dft16<true>(v);
     __syncthreads();  // previous chunk's FIR reads of lds are done
     {
@@ -383,7 +385,16 @@ lp_status syn_launch(lp_ctx *ctx, const SynPlan *p, int n_sb, const void *d,
   char *cb = static_cast<char *>(cand);
   SynCand *cd = reinterpret_cast<SynCand *>(cb);
   float *ps = reinterpret_cast<float *>(cb + (size_t)n_series * cand_nt * 8);
-  auto *kern = masked ? syn_kernel<true> : syn_kernel<false>;
+  // Kernel for the band's highest bin: pass-0 rows 4, 5, 6 or 8.
+  decltype(&syn_kernel<false, 8>) kern;
+  if (p->kmax < 256)
+    kern = masked ? syn_kernel<true, 4> : syn_kernel<false, 4>;
+  else if (p->kmax < 320)
+    kern = masked ? syn_kernel<true, 5> : syn_kernel<false, 5>;
+  else if (p->kmax < 384)
+    kern = masked ? syn_kernel<true, 6> : syn_kernel<false, 6>;
+  else
+    kern = masked ? syn_kernel<true, 8> : syn_kernel<false, 8>;
   hipLaunchKernelGGL(kern, dim3((unsigned)n_wg, n_series),
                      dim3(kSynThreads), 0, st, static_cast<const float2 *>(d),
                      static_cast<float2 *>(hist), p->binmap.as<const short>(),
