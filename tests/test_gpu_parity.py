@@ -282,6 +282,50 @@ def test_synthesis_warmup_statistics(frame0):
             assert env[q, m, arg[q, m]] >= (1 - 1e-5) * wmax[q, m], (q, m)
 
 
+@pytest.mark.parametrize("lo,hi", [(189, 221), (280, 312), (330, 362),
+                                   (480, 512), (1, 512)])
+def test_synthesis_band_rows(lo, hi):
+    """Synthesis of bands whose highest bin selects each transform variant
+    (pass-0 rows 4, 5, 6 and 8 of 64 bins): real series, window maxima,
+    arg-max and sigma against the oracle on the same FP32 subband samples."""
+    import torch
+
+    import oracle
+    rng = np.random.default_rng(lo * 1000 + hi)
+    k = np.arange(lo, hi)
+    S, n_t, ns = len(k), 2048, 2
+    d = (rng.standard_normal((ns, S, n_t))
+         + 1j * rng.standard_normal((ns, S, n_t))).astype(np.complex64)
+    ctx = lp.Ctx(0)
+    band = lp.Band(k)
+    dd = torch.from_numpy(d.view(np.float32).reshape(ns, S, n_t, 2)).to("cuda:0")
+    hist = torch.zeros(ns * S * 16 * 2, dtype=torch.float32, device="cuda:0")
+    cand = torch.empty(lp.nbytes("lp_cand_bytes", ns, n_t), dtype=torch.uint8,
+                       device="cuda:0")
+    xs = torch.empty((ns, n_t * 1024), dtype=torch.float32, device="cuda:0")
+    print(f"synthesis band {lo}..{hi - 1}", flush=True)
+    lp.synthesize(ctx, band, dd, ns, n_t, 0, hist, cand, x_out=xs)
+    torch.cuda.synchronize()
+    cb = cand.cpu().numpy()
+    x = xs.cpu().numpy()
+    c = cb[:ns * n_t * 8].view(np.float32).reshape(ns, n_t, 2)
+    emax, arg = c[..., 0], c[..., 1].view(np.int32)
+    psum = cb[ns * n_t * 8:ns * n_t * 8 + ns * (n_t // 16) * 4].view(
+        np.float32).reshape(ns, n_t // 16)
+    ctx.close()
+    z = oracle.synthesize(oracle.prototype(), k, d.astype(np.complex128),
+                          np.zeros((ns, 15, S), np.complex128))
+    sigma, wmax, warg = oracle.detect(z, n_t, 0, WARM)
+    assert rel_rms(x, 2 * z.real) <= 1e-5
+    assert rel_rms(emax, wmax) <= 1e-5
+    gs = np.sqrt(psum.astype(np.float64).sum(1) / ((n_t - WARM) * 1024))
+    assert np.max(np.abs(gs - sigma) / sigma) <= 1e-5
+    env = np.abs(2 * z).reshape(ns, n_t, 1024)
+    for q in range(ns):
+        for m in np.nonzero(arg[q] != warg[q] % 1024)[0]:
+            assert env[q, m, arg[q, m]] >= (1 - 1e-5) * wmax[q, m], (q, m)
+
+
 @pytest.mark.parametrize("case", ["c1", "c2s"])
 def test_plain_fp32_comparator(case):
     """The plain comparator pipeline matches the oracle at FP32 accuracy
