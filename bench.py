@@ -246,6 +246,41 @@ def main():
     found = sum(any(abs(int(t["sample"]) - (pl["n0"] + (a.warmup + a.steps - 1)
                                              * cfg.n_t * 1024)) <= 1
                     for t in trig) for pl in blk.pulses)
+    injected = sorted({int(pl["beam"]) for pl in blk.pulses})
+    # Per pulse: the beam of its highest-SNR trigger (a strong pulse's
+    # sidelobes also trigger neighbouring beams).
+    t_last = (a.warmup + a.steps - 1) * cfg.n_t * 1024
+    best_beam = []
+    for pl in blk.pulses:
+        near = [t for t in trig
+                if abs(int(t["sample"]) - (pl["n0"] + t_last)) <= 4]
+        best_beam.append(int(max(near, key=lambda t: t["snr"])["beam"])
+                         if near else None)
+    triggers = {"n": int(len(trig)),
+                "beams": sorted({int(t["beam"]) for t in trig}),
+                "injected_beams": [int(pl["beam"]) for pl in blk.pulses],
+                "best_trigger_beam_per_pulse": best_beam}
+    # TEC search: best trial and peak envelope SNR per trial of the beams
+    # that hold a pulse (last block).
+    tec_search = None
+    if cfg.n_tec > 1:
+        best = p.bufs["best"].cpu().numpy()
+        snr = p.bufs["snr"].cpu().numpy()
+        tec_search = {
+            "true_tec_index": cfg.true_tec_index,
+            "true_tec_tecu": float(cfg.true_tec),
+            "best_tec_index": {str(b): int(best[b]) for b in injected},
+            "peak_snr_vs_trial": {str(b): [round(float(v), 2) for v in snr[b]]
+                                  for b in injected}}
+    # The beamformer on the matrix cores: per subband the complex GEMM is
+    # the real GEMM [n_t x 2K] by [2K x 2B], 8 K B n_t FLOP.
+    mfma = None
+    if a.prec == "fp16":
+        fl = 8.0 * cfg.n_in * cfg.n_beams * cfg.n_t * cfg.n_sb
+        tf = fl / (stage_avg["beamform"] * 1e-3) / 1e12
+        mfma = {"kernel": "beamform", "achieved": round(tf, 2),
+                "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4),
+                "algorithmic_flop_per_launch": fl}
 
     ppf = None
     if a.ppf_iters > 0:
@@ -303,6 +338,9 @@ def main():
                        "deadline": round(deadline_ms, 1)},
         "stage_ms": {s: round(v, 4) for s, v in stage_avg.items()},
         "pulses_found": f"{found}/{len(blk.pulses)}",
+        "triggers": triggers,
+        "tec_search": tec_search,
+        "beamformer_mfma": mfma,
         "roofline": roofline,
         "plain_fp32_pipeline": plain,
         "ppf_inversion": ppf,
@@ -575,7 +613,7 @@ def serving_bench(a):
     dev = "cuda:0"
     specs = lofarsim.serving_streams(12, max_log2_nt=a.max_log2_nt)
     gen = torch.Generator(device=dev)
-    pools, cfgs = [], []
+    pools, cfgs, args = [], [], []
     for sp in specs:
         gen.manual_seed(sp["seed"])
         rng = np.random.default_rng(sp["seed"])
@@ -592,10 +630,10 @@ def serving_bench(a):
         enu = lofarsim.stations_in_disk(rng, sp["n_st"], 2000.0)
         az0, el0 = lofarsim.moon_direction(rng)
         rings = {7: 1, 19: 2, 37: 3, 61: 4}[sp["n_beams"]]
-        cfgs.append(lp.StreamCfg(enu, sp["k"], lofarsim.hex_beams(az0, el0, rings),
-                                 [sp["tec"]], 1 << a.max_log2_nt,
-                                 dtype=lp.LP_CI8, prec=lp.LP_FP16_MFMA,
-                                 trig_cap=256))
+        args.append((enu, sp["k"], lofarsim.hex_beams(az0, el0, rings),
+                     [sp["tec"]], 1 << a.max_log2_nt))
+        cfgs.append(lp.StreamCfg(*args[-1], dtype=lp.LP_CI8,
+                                 prec=lp.LP_FP16_MFMA, trig_cap=256))
     torch.cuda.synchronize()
     print(f"[bench] c5: {len(specs)} stream pools generated", file=sys.stderr,
           flush=True)
@@ -604,25 +642,37 @@ def serving_bench(a):
     arena_bytes = sum(c.resident_bytes(chunk_t) + c.block_bytes(1 << a.max_log2_nt)
                       for c in cfgs) + (1 << 30)
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
+    lens = [1 << e for e in range(12, a.max_log2_nt + 1)]
+
+    def calibrate(srv, ids):
+        """Service time alone: one block of each length per stream (the
+        first run also creates the stream's tables)."""
+        def run_alone(i, n_t):
+            srv.submit(ids[i], pools[i], n_t, tag=1 << 40)
+            while True:
+                r = srv.poll(timeout_us=1000000)
+                if r:
+                    return r[0]
+        svc = []
+        for i in range(len(ids)):
+            run_alone(i, lens[0])
+            t = [run_alone(i, n)["latency_ns"] * 1e-9 for n in lens]
+            svc.append(dict(zip(lens, t)))
+        return svc
+
+    # The same streams at FP32 (the fused path without the matrix cores),
+    # alone, for the precision comparison.
+    srv = lp.Server(ctx, arena, arena_bytes, max_slots=16, chunk_t=chunk_t)
+    cfgs32 = [lp.StreamCfg(*g, dtype=lp.LP_CI8, prec=lp.LP_FP32, trig_cap=256)
+              for g in args]
+    ids = [srv.open(c) for c in cfgs32]
+    svc32 = calibrate(srv, ids)
+    srv.destroy()
+
     srv = lp.Server(ctx, arena, arena_bytes, max_slots=16, chunk_t=chunk_t)
     ids = [srv.open(c) for c in cfgs]
     sbs = [c.array.n_in * c.band.n_sb * c.dirs.n for c in cfgs]
-
-    def run_alone(i, n_t):
-        srv.submit(ids[i], pools[i], n_t, tag=1 << 40)
-        while True:
-            r = srv.poll(timeout_us=1000000)
-            if r:
-                return r[0]
-
-    # Service time alone: one block of each length per stream (the first
-    # run also creates the stream's tables); a linear fit per stream.
-    lens = [1 << e for e in range(12, a.max_log2_nt + 1)]
-    svc = []
-    for i in range(len(ids)):
-        run_alone(i, lens[0])
-        t = [run_alone(i, n)["latency_ns"] * 1e-9 for n in lens]
-        svc.append(dict(zip(lens, t)))
+    svc = calibrate(srv, ids)
     mean_svc = [float(np.mean(list(d.values()))) for d in svc]
     rate = [a.load / (len(ids) * m) for m in mean_svc]   # blocks per second
     print(f"[bench] c5: calibrated; mean service ms "
@@ -683,6 +733,12 @@ def serving_bench(a):
                    "chunks": stats["chunks_issued"],
                    "admit_waits": stats["admit_waits"]},
         "measured_load": round(busy / wall, 3),
+        # Sum over streams and block lengths of the time alone per block.
+        "service_alone_s": {
+            "fp16_mfma": round(sum(sum(d.values()) for d in svc), 4),
+            "fp32": round(sum(sum(d.values()) for d in svc32), 4),
+            "fp32_over_fp16": round(sum(sum(d.values()) for d in svc32)
+                                    / sum(sum(d.values()) for d in svc), 3)},
     }
     print(json.dumps(out))
 
