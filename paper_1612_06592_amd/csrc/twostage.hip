@@ -14,8 +14,8 @@
 //   y[b][s][t] = sum_g exp(-2 pi i frac(f_s r_g . (n_b - n_p(b)) / c))
 //                y1[g P + p(b)][s][t].
 // The coefficients are formed on the host in FP64 once per plan.  The
-// kernel holds one time sample of every group's preliminary beam in
-// registers and writes every final beam that uses it (coalesced in t).
+// kernel holds one or two time samples of every group's preliminary beam
+// in registers and writes every final beam that uses them (coalesced in t).
 #include <algorithm>
 #include <cmath>
 
@@ -26,6 +26,10 @@ namespace lp {
 constexpr int kTsThreads = 256;
 constexpr int kTsMaxGroups = 32;
 
+// NS samples per thread (1, or 2 with 16-byte accesses when n_t is even
+// and both arrays are 16-byte aligned); GMAX >= G bounds the registers
+// that hold the groups' samples.
+template <int NS, int GMAX>
 __global__ __launch_bounds__(kTsThreads) void ts_stage2_kernel(
     const float2 *__restrict__ y1, const float2 *__restrict__ coef,
     const int *__restrict__ order, const int *__restrict__ pstart, int G,
@@ -35,29 +39,47 @@ __global__ __launch_bounds__(kTsThreads) void ts_stage2_kernel(
   for (int i = threadIdx.x; i < B * G; i += kTsThreads)
     cs[i] = coef[(long)s * B * G + i];
   __syncthreads();
-  const long t = (long)blockIdx.x * kTsThreads + threadIdx.x;
+  const long t = ((long)blockIdx.x * kTsThreads + threadIdx.x) * NS;
   if (t >= n_t) return;
   for (int p = 0; p < P; ++p) {
     const int b0 = pstart[p], b1 = pstart[p + 1];
     if (b0 == b1) continue;
-    float2 v[kTsMaxGroups];
+    // v[g][k]: sample t + k of group g's preliminary beam p.
+    float2 v[GMAX][NS];
 #pragma unroll
-    for (int g = 0; g < kTsMaxGroups; ++g)
-      v[g] = (g < G) ? y1[((long)(g * P + p) * n_sb + s) * n_t + t]
-                     : make_float2(0.f, 0.f);
+    for (int g = 0; g < GMAX; ++g) {
+      const float2 *src = y1 + ((long)(g * P + p) * n_sb + s) * n_t + t;
+      if constexpr (NS == 2) {
+        const float4 q = (g < G) ? *reinterpret_cast<const float4 *>(src)
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+        v[g][0] = make_float2(q.x, q.y);
+        v[g][1] = make_float2(q.z, q.w);
+      } else {
+        v[g][0] = (g < G) ? *src : make_float2(0.f, 0.f);
+      }
+    }
     for (int i = b0; i < b1; ++i) {
       const int b = order[i];
       const float2 *c = cs + b * G;
-      float ar = 0.f, ai = 0.f;
+      float ar[NS], ai[NS];
 #pragma unroll
-      for (int g = 0; g < kTsMaxGroups; ++g) {
+      for (int k = 0; k < NS; ++k) ar[k] = ai[k] = 0.f;
+#pragma unroll
+      for (int g = 0; g < GMAX; ++g) {
         if (g < G) {
           const float2 w = c[g];
-          ar = fmaf(w.x, v[g].x, fmaf(-w.y, v[g].y, ar));
-          ai = fmaf(w.x, v[g].y, fmaf(w.y, v[g].x, ai));
+#pragma unroll
+          for (int k = 0; k < NS; ++k) {
+            ar[k] = fmaf(w.x, v[g][k].x, fmaf(-w.y, v[g][k].y, ar[k]));
+            ai[k] = fmaf(w.x, v[g][k].y, fmaf(w.y, v[g][k].x, ai[k]));
+          }
         }
       }
-      y[((long)b * n_sb + s) * n_t + t] = make_float2(ar, ai);
+      float2 *dst = y + ((long)b * n_sb + s) * n_t + t;
+      if constexpr (NS == 2)
+        *reinterpret_cast<float4 *>(dst) = make_float4(ar[0], ai[0], ar[1], ai[1]);
+      else
+        *dst = make_float2(ar[0], ai[0]);
     }
   }
 }
@@ -281,9 +303,16 @@ extern "C" lp_status lp_beamform_stage2(lp_ctx *ctx, const lp_array *array,
   if ((rc = get_ts_plan(ctx, array, groups, band, prelim, n_prelim, beams,
                         n_beams, &p)))
     return rc;
-  dim3 grid((unsigned)((n_t + kTsThreads - 1) / kTsThreads), band->n_sb);
+  const bool two = n_t % 2 == 0 && reinterpret_cast<uintptr_t>(y1) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(y) % 16 == 0;
+  const long per_wg = (long)kTsThreads * (two && p->G <= 8 ? 2 : 1);
+  dim3 grid((unsigned)((n_t + per_wg - 1) / per_wg), band->n_sb);
   size_t shm = (size_t)p->B * p->G * sizeof(float2);
-  hipLaunchKernelGGL(ts_stage2_kernel, grid, dim3(kTsThreads), shm,
+  // (Two samples of up to 32 groups would take 145 registers.)
+  auto *kern = p->G > 8 ? ts_stage2_kernel<1, kTsMaxGroups>
+               : two    ? ts_stage2_kernel<2, 8>
+                        : ts_stage2_kernel<1, 8>;
+  hipLaunchKernelGGL(kern, grid, dim3(kTsThreads), shm,
                      static_cast<hipStream_t>(hip_stream),
                      static_cast<const float2 *>(y1), p->coef.as<const float2>(),
                      p->order.as<const int>(), p->pstart.as<const int>(),

@@ -80,23 +80,26 @@ def test_stages_match_oracle():
         assert e1 <= TOL[prec] and e2 <= TOL[prec]
 
 
-def test_stage2_alone_and_identities():
+@pytest.mark.parametrize("n_t,G", [(1000, 5), (999, 5), (1000, 9)])
+def test_stage2_alone_and_identities(n_t, G):
     """Stage 2 on the oracle's own stage-1 beams (FP32 input), and the exact
     identity: a final beam at a preliminary direction is the sum of the
-    groups' beams, i.e. the single-stage beam."""
+    groups' beams, i.e. the single-stage beam.  Even n_t takes the kernel
+    with two samples per thread, odd n_t one; more than 8 groups take the
+    kernel sized for 32."""
     import torch
-    cfg = lofarsim.get_config("c3", n_t=1000, hex_rings=1,
+    cfg = lofarsim.get_config("c3", n_t=n_t, hex_rings=1,
                               k=tuple(range(200, 212)), n_pulses=0)
     blk = lofarsim.generate(cfg, with_noise=True)
-    group, prelim = _geometry(blk, G=5)
-    G, P = 5, len(prelim)
+    group, prelim = _geometry(blk, G=G)
+    P = len(prelim)
     finals = np.concatenate([blk.az_el, prelim[3:5]])
     o1 = ts.stage1(blk.enu, 2, group, G, blk.k, prelim, blk.x)
     o2 = ts.stage2(blk.enu, group, G, blk.k, prelim, finals, o1)
     ctx = lp.Ctx(0)
     y = torch.empty((len(finals), len(blk.k), blk.n_t, 2),
                     dtype=torch.float32, device="cuda:0")
-    print("case stage2 alone, n_t=1000 (ragged), 5 groups", flush=True)
+    print(f"case stage2 alone, n_t={n_t} (ragged), {G} groups", flush=True)
     lp.beamform_stage2(ctx, lp.Array(blk.enu, 2), lp.Groups(group, G),
                        lp.Band(blk.k), lp.Dirs(prelim), lp.Dirs(finals),
                        _dev_c(o1), blk.n_t, y)
