@@ -43,10 +43,11 @@ def test_adc_codes_bit_exact():
     ctx.close()
 
 
+@pytest.mark.parametrize("n_in", [4, 8])
 @pytest.mark.parametrize("dtype,bits", [(lp.LP_CI8, 8), (lp.LP_CI16, 16)])
-def test_station_ppf_matches_oracle(dtype, bits):
+def test_station_ppf_matches_oracle(dtype, bits, n_in):
     import torch
-    n_in, nf = 4, 300
+    nf = 300
     k = np.arange(52, 84)
     h = oracle.prototype(M, P, 9.0)
     codes = ss.adc(77, n_in, 16, 12, 1, (nf + P - 1) * M)
@@ -62,7 +63,8 @@ def test_station_ppf_matches_oracle(dtype, bits):
                     device="cuda:0")
     work = torch.empty(lp.nbytes("lp_station_work_bytes", n_in, len(k), nf),
                        dtype=torch.uint8, device="cuda:0")
-    print(f"case station ppf n_in=4 nf=300 32 subbands, {bits}-bit", flush=True)
+    print(f"case station ppf n_in={n_in} nf=300 32 subbands, {bits}-bit",
+          flush=True)
     lp.station_ppf(ctx, band, adc, n_in, nf, float(scale), x, work, dtype)
     torch.cuda.synchronize()
     got = x.cpu().numpy()
