@@ -202,7 +202,8 @@ lp_status lp_beamform_groups(lp_ctx *ctx, const lp_array *array,
  *                y1[g * n_prelim + p(b)][s][t]
  * (coefficients in FP64, applied in FP32).  y1 as written by
  * lp_beamform_groups; y is cf32 [n_beams][n_sb][n_t], n_beams <= 64, any
- * n_t > 0; 8-byte aligned buffers.                                         */
+ * n_t > 0; 8-byte aligned buffers (with at most 8 groups, an even n_t and
+ * 16-byte aligned y1 and y the kernel moves two samples per access).      */
 lp_status lp_beamform_stage2(lp_ctx *ctx, const lp_array *array,
                              const lp_groups *groups, const lp_band *band,
                              const lp_dir *prelim, int32_t n_prelim,
@@ -345,7 +346,8 @@ lp_status lp_sim_adc(lp_ctx *ctx, const lp_sim_cfg *cfg, int64_t n0,
  * half to even and saturated to the int8 or int16 range (dtype LP_CI8 or
  * LP_CI16), written as the beamformer's input x [n_sb][n_frames][n_in]
  * complex.  n_in <= 128, n_frames <= 2^19 - 30.  work: device, >=
- * lp_station_work_bytes().                                                  */
+ * lp_station_work_bytes().  (n_in a multiple of 8 for LP_CI8, of 4 for
+ * LP_CI16, with 16-byte aligned x and work, takes 16-byte stores.)          */
 size_t lp_station_work_bytes(int32_t n_in, int32_t n_sb, int64_t n_frames);
 lp_status lp_station_ppf(lp_ctx *ctx, const lp_band *band, const int16_t *adc,
                          int32_t n_in, int64_t n_frames, float scale,
