@@ -571,7 +571,10 @@ def run_cpu_baseline(blk, hops: int):
            "seconds": round(dt, 2), "cpu_model": cpu_model(),
            "nproc": os.cpu_count()}
     # The same chain on one thread, over its first hop only (a fresh
-    # stream, so the same arithmetic as the first hop above).
+    # stream, so the same arithmetic as the first hop above); for the
+    # single-beam, single-trial workloads (C1, C2), where it takes seconds.
+    if cfg.n_beams * cfg.n_tec > 1:
+        return out
     n1 = min(2048, n)
     cores = oracle.threads()
     oracle.set_threads(1)
