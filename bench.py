@@ -33,6 +33,7 @@ FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (256 CU, 2.4 GHz, packed)
 METRIC = ("station-beam Msamples/s real-time factor at ≤1e-3 rel RMS; "
           "p99 block latency")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+LSMR_ITERS = 25                # iterations of the PPF-inversion leg (Sec. 3)
 
 
 def kernel_source_hash(name: str) -> str:
@@ -76,14 +77,20 @@ def device_copy_gbs(dev, mib: int = 1024, reps: int = 5) -> float:
 
 
 def algorithmic_flop(stage: str, cfg, n_t: int) -> float:
-    """FLOP a launch must do (the paper's 5 N log2 N per FFT): de-dispersion
-    120 per beam-subband-sample for the forward transforms (half-overlapped
-    4096-point FFTs) plus 126 per trial (chirp and inverse); synthesis 120
-    per 5 ns output sample (50 for the 1024-point transform, 64 for the
-    16-tap complex FIR, 6 for envelope and statistics)."""
-    S, B, J = cfg.n_sb, cfg.n_beams, cfg.n_tec
+    """FLOP a launch must do, by the paper's cost rules (Sec. 3: 8 FLOP per
+    station sample and beam for beamforming, 6 per complex multiply,
+    5 N log2 N per N-point FFT).  Beamforming: 8 per input (station-
+    polarisation) sample, subband and beam.  De-dispersion, per
+    beam-subband-sample (each 4096-point transform yields 2048 new
+    samples): 120 for the forward transforms, plus per trial 12 for the
+    chirp (4096 products) and 120 for the inverse.  Synthesis, per 5 ns
+    output sample: 50 for the 1024-point transform, 64 for the 16-tap
+    complex-by-real FIR, 6 for envelope and statistics."""
+    K, S, B, J = cfg.n_in, cfg.n_sb, cfg.n_beams, cfg.n_tec
+    if stage == "beamform":
+        return 8.0 * K * S * n_t * B
     if stage == "dedisperse":
-        return B * S * n_t * (120.0 + 126.0 * J)
+        return B * S * n_t * (120.0 + 132.0 * J)
     if stage == "synthesize":
         return B * J * n_t * 1024 * 120.0
     return 0.0
@@ -107,7 +114,7 @@ def main():
                     help="c5: offered load as a fraction of the GPU")
     ap.add_argument("--max-log2-nt", type=int, default=18,
                     help="c5: longest block is 2^this samples per subband")
-    ap.add_argument("--ppf-iters", type=int, default=25,
+    ap.add_argument("--ppf-iters", type=int, default=LSMR_ITERS,
                     help="LSMR iterations of the PPF-inversion leg (0: skip)")
     ap.add_argument("--ppf-steps", type=int, default=3,
                     help="timed PPF-inversion solves")
@@ -276,7 +283,7 @@ def main():
     # the real GEMM [n_t x 2K] by [2K x 2B], 8 K B n_t FLOP.
     mfma = None
     if a.prec == "fp16":
-        fl = 8.0 * cfg.n_in * cfg.n_beams * cfg.n_t * cfg.n_sb
+        fl = algorithmic_flop("beamform", cfg, cfg.n_t)
         tf = fl / (stage_avg["beamform"] * 1e-3) / 1e12
         mfma = {"kernel": "beamform", "achieved": round(tf, 2),
                 "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4),
