@@ -369,7 +369,7 @@ lp_status syn_launch(lp_ctx *ctx, const SynPlan *p, int n_sb, const void *d,
   // multiple of 2048, so every candidate divides it.
   int F = 16;
   double best = -1.0;
-  for (int f : {1024, 512, 256, 128, 64, 32, 16}) {
+  for (int f : {2048, 1024, 512, 256, 128, 64, 32, 16}) {
     const long nw = (long)n_series * (n_t / f);
     const long rounds = (nw + ctx->n_cu - 1) / ctx->n_cu;
     const double eff =
