@@ -30,6 +30,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (256 CU, 2.4 GHz, packed)
+FP32_UNPACKED_TFLOPS = 78.6    # the same without packed FP32 instructions,
+                               # which the library's compile flags disable
 METRIC = ("station-beam Msamples/s real-time factor at ≤1e-3 rel RMS; "
           "p99 block latency")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
@@ -246,7 +248,10 @@ def main():
                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                     "traffic": traffic, "algorithmic_flop_per_launch": flop,
                     "algorithmic_bytes_per_launch": alg,
-                    "avg_launch_ms": round(stage_avg[dom], 4)}
+                    "avg_launch_ms": round(stage_avg[dom], 4),
+                    "unpacked_peak": FP32_UNPACKED_TFLOPS,
+                    "frac_of_unpacked_peak": round(
+                        achieved / FP32_UNPACKED_TFLOPS, 4)}
 
     # Trigger sanity on the last block: the injected pulses are found.
     trig = p.triggers()
