@@ -270,7 +270,10 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     const int first_valid = fv <= 0 ? 0 : (fv >= 16 ? 16 : (int)fv);
     float *xo = x_out ? x_out + ((long)series * n_t + mc) * 1024 + no : nullptr;
     // (zr, zi) = 2 z of frame fi: 2 Re z is the real series, |2 z|^2 the
-    // squared envelope; the slot is consumed, so it takes the latter.
+    // squared envelope; the slot is consumed, so it takes the latter, in
+    // its x word for columns with bit 4 clear and its y word otherwise (the
+    // 16-column groups then alternate between even and odd banks).
+    const int ecomp = (no >> 4) & 1;
 #pragma unroll
     for (int fi = 0; fi < 16; ++fi) {
       float2 *slot = lds + fi * kSynFs + pad16(no);
@@ -284,7 +287,7 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
       }
       if (!MASKED || fi >= first_valid) acc_s = fmaf(zr, zr, acc_s);
       if (xo) xo[(long)fi * 1024] = zr;
-      slot->x = zr * zr + zi * zi;
+      reinterpret_cast<float *>(slot)[ecomp] = zr * zr + zi * zi;
     }
     if (!MASKED && first_valid != 0) acc_s = 0.f;  // first_valid is 16
     acc_s = wave_sum_dpp(acc_s);
@@ -296,11 +299,14 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     // Squared envelopes are >= +0, so their bit patterns order as unsigned
     // integers: the maximum is an exact selection.
     {
-      // Lane l holds n = l + 64 i at slot pad16(n) = l + l / 16 + 68 i.
-      const float2 *fl = lds + wo * kSynFs + lo + (lo >> 4);
+      // Lane l holds n = l + 64 i at slot pad16(n) = l + l / 16 + 68 i,
+      // envelope word (n / 16) mod 2 = (l / 16) mod 2.
+      const float *fl = reinterpret_cast<const float *>(
+                            lds + wo * kSynFs + lo + (lo >> 4)) +
+                        ((lo >> 4) & 1);
       unsigned e2[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) e2[i] = __float_as_uint(fl[68 * i].x);
+      for (int i = 0; i < 16; ++i) e2[i] = __float_as_uint(fl[2 * 68 * i]);
       unsigned bv = e2[0];
 #pragma unroll
       for (int i = 1; i < 16; ++i) bv = max(bv, e2[i]);
