@@ -18,7 +18,7 @@
 namespace lp {
 
 constexpr int kDdThreads = 256;
-constexpr int kDdLds = 4096 + 256;  // pad16 of 4095 is 4350
+constexpr int kDdLds = 4096 + 128;  // slot of element 4095 is 4222
 
 // 4096-point transform of v[r] = in[j + 256 r] (j = thread); on return
 // v[r] = out[j + 256 r].  Unnormalised; INV selects exp(+2 pi i ...).
@@ -58,19 +58,24 @@ template <bool INV>
 __device__ __forceinline__ void fft4096(float2 *v, float2 *lds,
                                         const float2 *coarse,
                                         const float2 *fine, int j) {
-  // LDS slots in closed form (j < 256, r < 16):
-  //   pad16(16 j + r) = 17 j + r,  pad16(j + 256 r) = j + j / 16 + 272 r,
-  //   pad16((j / 16) 256 + j mod 16 + 16 r) = (j / 16) 272 + j mod 16 + 17 r.
-  const int sj = j + (j >> 4);
+  // Element e sits at slot e + e / 32 (one pad slot per 32: every access
+  // pattern below puts the 64 lanes' 8-byte words evenly on the banks, for
+  // 32 or 64 banks).  In closed form (j < 256, r < 16):
+  //   16 j + r -> 16 j + j / 2 + r,  j + 256 r -> j + j / 32 + 264 r,
+  //   (j / 16) 256 + j mod 16 + 16 r -> (j / 16) 264 + j mod 16 + 16 r + r / 2.
+  const int sj = j + (j >> 5);
   // Pass 0 (Ns = 1): no twiddle; write to (16 j + r).
   dft16<INV>(v);
   __syncthreads();
+  {
+    const int b0 = 16 * j + (j >> 1);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) lds[17 * j + r] = v[r];
+    for (int r = 0; r < 16; ++r) lds[b0 + r] = v[r];
+  }
   __syncthreads();
   // Pass 1 (Ns = 16).
 #pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = lds[sj + 272 * r];
+  for (int r = 0; r < 16; ++r) v[r] = lds[sj + 264 * r];
   {
     const float2 w = coarse[j & 15];  // angle 2 pi (j mod 16) / 256
     pow16_twiddle(v, INV ? make_float2(w.x, -w.y) : w);
@@ -78,14 +83,14 @@ __device__ __forceinline__ void fft4096(float2 *v, float2 *lds,
   dft16<INV>(v);
   __syncthreads();
   {
-    const int b2 = (j >> 4) * 272 + (j & 15);
+    const int b2 = (j >> 4) * 264 + (j & 15);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) lds[b2 + 17 * r] = v[r];
+    for (int r = 0; r < 16; ++r) lds[b2 + 16 * r + (r >> 1)] = v[r];
   }
   __syncthreads();
   // Pass 2 (Ns = 256): output index j + 256 r stays in registers.
 #pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = lds[sj + 272 * r];
+  for (int r = 0; r < 16; ++r) v[r] = lds[sj + 264 * r];
   pow16_twiddle(v, tw4096_lds<INV>(coarse, fine, j));
   dft16<INV>(v);
 }
