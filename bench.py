@@ -103,11 +103,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c3",
+                    help="c1 tiny, c2 single beam, c3 61 beams (default: the "
+                         "largest single-GPU workload by station-beam "
+                         "samples), c4 32 TEC trials, c5 serving")
     ap.add_argument("--prec", default="fp16", choices=["fp16", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-hops", type=int, default=32,
-                    help="hops (2048 samples each) in the oracle sample")
+    ap.add_argument("--cpu-beams", type=int, default=0,
+                    help="beams in the oracle's sample of the first block "
+                         "(0: the pulses' beams, then others, up to "
+                         "max(1, 8 // trials))")
     ap.add_argument("--plain-steps", type=int, default=3,
                     help="steps of the plain FP32 comparator pipeline (0: skip)")
     ap.add_argument("--duration", type=float, default=20.0,
@@ -163,6 +168,15 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    # The first block of the fresh stream, kept for the error leg: the
+    # sampled beams' beam sums, de-dispersed subbands, window maxima,
+    # sigma, peak SNR and triggers.
+    sel = sample_beams(cfg, blk, a.cpu_beams)
+    p.step(x)
+    torch.cuda.synchronize()
+    first = first_block_outputs(p, sel)
+    print(f"[bench] first block kept for beams {sel}", file=sys.stderr,
+          flush=True)
     # The trigger of block i (one workgroup per series) runs on a second
     # stream while block i + 1 is beamformed and de-dispersed; synthesis of
     # block i + 1 waits for it, since it overwrites the candidates.
@@ -327,9 +341,9 @@ def main():
         del pp
         torch.cuda.empty_cache()
 
-    cpu = None
+    cpu = error = None
     if not a.no_cpu_baseline:
-        cpu = run_cpu_baseline(blk, a.cpu_hops)
+        cpu, error = run_cpu_baseline(blk, sel, first)
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Msamples/s",
@@ -354,6 +368,8 @@ def main():
         "tec_search": tec_search,
         "beamformer_mfma": mfma,
         "roofline": roofline,
+        "whole_step": whole_step(cfg, ms_per_step),
+        "error_vs_oracle": error,
         "plain_fp32_pipeline": plain,
         "ppf_inversion": ppf,
         "two_stage_beamforming": two,
@@ -563,31 +579,131 @@ def ppf_cpu_baseline(cfg, d, iters: int, frames: int = 1024):
                       f"of series 0", "seconds": round(dt, 2)}
 
 
-def run_cpu_baseline(blk, hops: int):
-    """Time the oracle chain (as it stands) on the first `hops` hops of the
-    block: all subbands, inputs, beams and trials of that time range."""
+def sample_beams(cfg, blk, n_beams: int = 0):
+    """Beams of the oracle's sample: the injected pulses' beams first, then
+    the lowest others, up to n_beams (0: max(1, 8 // trials))."""
+    B = cfg.n_beams
+    n = n_beams or max(1, 8 // cfg.n_tec)
+    n = min(n, B)
+    sel = []
+    for pl in blk.pulses:
+        b = int(pl["beam"])
+        if b not in sel and len(sel) < n:
+            sel.append(b)
+    for b in range(B):
+        if len(sel) >= n:
+            break
+        if b not in sel:
+            sel.append(b)
+    return sorted(sel)
+
+
+def first_block_outputs(p, sel):
+    """Host copies of the sampled beams' outputs of the block just run."""
+    import torch
+    idx = torch.tensor(sel, device=p.bufs["y"].device)
+    J, n_t = p.n_tec, p.n_t
+    emax, _, _ = p.cand_view()
+    qs = [b * J + j for b in sel for j in range(J)]
+    q = torch.tensor(qs, device=idx.device)
+    trig = p.triggers()
+    return dict(
+        y=p.y_view().index_select(0, idx).cpu().numpy(),
+        d=p.d_view().index_select(0, idx).cpu().numpy(),
+        emax=emax.index_select(0, q).cpu().numpy(),
+        sigma=p.bufs["sigma"].index_select(0, idx).cpu().numpy().ravel(),
+        snr=p.bufs["snr"].index_select(0, idx).cpu().numpy().ravel(),
+        best=p.bufs["best"].index_select(0, idx).cpu().numpy(),
+        trig=trig[np.isin(trig["beam"], sel)],
+        n_trig=int(p.bufs["n_trig"].item()), n_kept=len(trig), n_t=n_t)
+
+
+def _c(a):
+    return a[..., 0].astype(np.float64) + 1j * a[..., 1].astype(np.float64)
+
+
+def _rel_rms(a, b) -> float:
+    return float(np.sqrt(np.sum(np.abs(a - b) ** 2) / np.sum(np.abs(b) ** 2)))
+
+
+def compare_trigger_lists(g, o, k_sigma: float, tol: int = 1,
+                          border: float = 0.01):
+    """Beam exact, sample within tol; a trigger without partner whose SNR is
+    within `border` (relative) of the threshold is a borderline decision
+    (FP16 and FP64 envelopes differ by ~1e-4) and is listed, not failed."""
+    used, missing, border_n = set(), 0, 0
+    for t in o:
+        hit = None
+        for i, u in enumerate(g):
+            if i not in used and int(u["beam"]) == int(t["beam"]) and \
+                    abs(int(u["sample"]) - int(t["sample"])) <= tol:
+                hit = i
+                break
+        if hit is None:
+            if abs(t["snr"] / k_sigma - 1.0) > border:
+                missing += 1
+            else:
+                border_n += 1
+        else:
+            used.add(hit)
+    extra = 0
+    for i, u in enumerate(g):
+        if i not in used:
+            if abs(u["snr"] / k_sigma - 1.0) > border:
+                extra += 1
+            else:
+                border_n += 1
+    return {"equal": missing == 0 and extra == 0, "gpu": int(len(g)),
+            "oracle": int(len(o)), "missing": missing, "extra": extra,
+            "borderline": border_n}
+
+
+def run_cpu_baseline(blk, sel, first):
+    """Time the oracle chain (as it stands) on the sampled beams of the
+    first block (fresh stream: all subbands, inputs, trials and samples),
+    and compare the GPU's outputs of that block with it."""
     import oracle
     cfg = blk.cfg
-    n = min(hops * 2048, blk.n_t)
-    xs = blk.x[:, :n]
-    st = oracle.Stream(blk.enu, 2, blk.k, blk.az_el, blk.tec)
+    n_t = blk.n_t
+    st = oracle.Stream(blk.enu, 2, blk.k, blk.az_el[sel], blk.tec,
+                       series_group=4, keep_z=False)
     t0 = time.perf_counter()
-    st.process(xs)
+    r = st.process(blk.x)
     dt = time.perf_counter() - t0
-    samples = cfg.n_in * cfg.n_sb * n * cfg.n_beams
+    samples = cfg.n_in * cfg.n_sb * n_t * len(sel)
     out = {"value": round(samples / dt / 1e6, 3), "unit": "Msamples/s",
            "cores": oracle.threads(), "kind": "oracle",
-           "sample": f"first {n} of {blk.n_t} samples per subband "
-                     f"(all {cfg.n_sb} subbands, {cfg.n_in} inputs, "
-                     f"{cfg.n_beams} beams, {cfg.n_tec} trials)",
+           "sample": f"first block (fresh stream), beams {sel} of "
+                     f"{cfg.n_beams}: all {cfg.n_sb} subbands, {cfg.n_in} "
+                     f"inputs, {cfg.n_tec} trials, {n_t} samples",
            "seconds": round(dt, 2), "cpu_model": cpu_model(),
            "nproc": os.cpu_count()}
+    o_trig = r.triggers.copy()
+    o_trig["beam"] = np.asarray(sel)[o_trig["beam"]]
+    err = {"block": "first (fresh stream)", "beams": sel,
+           "y_rel_rms": _rel_rms(_c(first["y"]), r.y),
+           "d_rel_rms": _rel_rms(_c(first["d"]), r.d),
+           "window_max_rel_rms": _rel_rms(first["emax"].astype(np.float64),
+                                          r.wmax),
+           "sigma_max_rel": float(np.max(np.abs(first["sigma"] - r.sigma)
+                                         / r.sigma)),
+           "peak_snr_max_rel": float(np.max(
+               np.abs(first["snr"] - r.snr_peak.ravel())
+               / np.maximum(r.snr_peak.ravel(), 1e-30))),
+           "best_tec_equal": bool(np.array_equal(first["best"], r.best_tec)),
+           "triggers": compare_trigger_lists(first["trig"], o_trig, 6.0),
+           "bound": 1e-3}
+    err["within_bound"] = bool(
+        max(err["y_rel_rms"], err["d_rel_rms"],
+            err["window_max_rel_rms"]) <= 1e-3 and
+        err["triggers"]["equal"] and err["best_tec_equal"] and
+        first["n_trig"] == first["n_kept"])
     # The same chain on one thread, over its first hop only (a fresh
     # stream, so the same arithmetic as the first hop above); for the
     # single-beam, single-trial workloads (C1, C2), where it takes seconds.
     if cfg.n_beams * cfg.n_tec > 1:
-        return out
-    n1 = min(2048, n)
+        return out, err
+    n1 = min(2048, n_t)
     cores = oracle.threads()
     oracle.set_threads(1)
     try:
@@ -601,7 +717,22 @@ def run_cpu_baseline(blk, hops: int):
         "value": round(cfg.n_in * cfg.n_sb * n1 * cfg.n_beams / dt1 / 1e6, 3),
         "unit": "Msamples/s", "sample": f"first {n1} samples per subband",
         "seconds": round(dt1, 2)}
-    return out
+    return out, err
+
+
+def whole_step(cfg, ms_per_step: float):
+    """The whole chain per step against both rooflines: algorithmic HBM
+    bytes and FP32 FLOP of beamform + de-dispersion + synthesis."""
+    n_t = cfg.n_t
+    by = sum(algorithmic_bytes(s, cfg, n_t)
+             for s in ("beamform", "dedisperse", "synthesize"))
+    fl = sum(algorithmic_flop(s, cfg, n_t)
+             for s in ("dedisperse", "synthesize"))
+    sec = ms_per_step * 1e-3
+    return {"hbm_bytes": by, "GBps": round(by / sec / 1e9, 1),
+            "frac_hbm": round(by / sec / 1e9 / HBM_PEAK_GBS, 4),
+            "fp32_flop": fl, "TFLOPs": round(fl / sec / 1e12, 2),
+            "frac_fp32": round(fl / sec / 1e12 / FP32_PEAK_TFLOPS, 4)}
 
 
 def cpu_model() -> str:

@@ -47,8 +47,13 @@
  * stated otherwise arguments named *_state are read and updated in place
  * and are all-zero for a fresh stream.  Descriptors (lp_array, lp_band,
  * lp_dir, TEC lists) are host memory read during the call only.  Device
- * tables derived from descriptors (beam weights, chirp constants) are
- * cached inside the lp_ctx.
+ * tables derived from descriptors (beam weights, chirp constants, synthesis
+ * taps) are cached in the lp_ctx as "plans": a new plan's tables are written
+ * asynchronously on the stream of the call that needs them (no device-wide
+ * synchronisation), by default into memory the library allocates, or into
+ * a caller buffer bound with lp_ctx_bind_const.  At most lp_ctx_plan_cache
+ * plans (default 64) are kept beyond those in use; the least recently used
+ * one is evicted (after waiting for the device) when a new one is made.
  *
  * Errors: nothing throws across the ABI.  Argument errors return
  * LP_EINVAL synchronously and leave every buffer untouched; the message is
@@ -137,6 +142,21 @@ const char *lp_version(void);
 lp_status lp_ctx_create(int32_t hip_device, lp_ctx **out);
 void lp_ctx_destroy(lp_ctx *ctx);
 
+/* Take plan tables from a caller buffer: device memory [bytes], 256-byte
+ * aligned, that the caller keeps allocated until lp_ctx_destroy or the next
+ * bind.  Cached plans are dropped first (after waiting for the device);
+ * LP_EINVAL if a plan is in use (an open serving stream).  dev = NULL goes
+ * back to library-allocated tables.  When a new plan does not fit, unused
+ * plans are evicted; if it still does not fit the call that needed it
+ * returns LP_ENOMEM.  (A C2-sized band needs about 5 MB per chirp plan and
+ * 0.2-12 MB per beam-weight plan.)                                         */
+lp_status lp_ctx_bind_const(lp_ctx *ctx, void *dev, size_t bytes);
+/* Keep at most max_plans cached plans that no call or stream is using.    */
+lp_status lp_ctx_plan_cache(lp_ctx *ctx, int32_t max_plans);
+/* Cached plans, those in use, and their device bytes (any may be NULL).   */
+lp_status lp_ctx_plan_stats(lp_ctx *ctx, int32_t *n_plans, int32_t *n_held,
+                            size_t *device_bytes);
+
 /* ---- sizing helpers (bytes of caller-allocated device buffers) -------- */
 /* y of lp_beamform: cf32 [n_beams][n_sb][n_t]                              */
 size_t lp_beam_bytes(int32_t n_beams, int32_t n_sb, int64_t n_t);
@@ -150,8 +170,10 @@ size_t lp_syn_state_bytes(int32_t n_series, int32_t n_sb);
  * maximum (f32) and its offset in the frame (i32), then per series and
  * 16-frame chunk the FP32 sum of (2 Re z)^2 over valid samples.          */
 size_t lp_cand_bytes(int32_t n_series, int64_t n_t);
-/* work of lp_trigger                                                       */
-size_t lp_trigger_work_bytes(int32_t n_beams, int32_t n_tec);
+/* work of lp_trigger: per series room for every run a block of n_t windows
+ * can hold (n_t / 2), about n_beams * n_tec * n_t * 8 bytes; 0 on invalid
+ * sizes.                                                                   */
+size_t lp_trigger_work_bytes(int32_t n_beams, int32_t n_tec, int64_t n_t);
 
 /* ---- the hot path ------------------------------------------------------ */
 
@@ -159,9 +181,14 @@ size_t lp_trigger_work_bytes(int32_t n_beams, int32_t n_tec);
  *   x : device, [n_sb][n_t][n_st][n_pol] complex int (dtype LP_CI8 or
  *       LP_CI16), re/im interleaved, inputs contiguous.
  *   y : device, cf32 [n_beams][n_sb][n_t] (lp_beam_bytes), overwritten.
- *   prec: LP_FP32 or LP_FP16_MFMA.  In FP16 each input's weights are scaled
- *       to unit peak magnitude by a power of two that is moved, exactly, onto
- *       the input's samples (int8 and |int16| <= 2048 are exact in FP16).
+ *   prec: LP_FP32 or LP_FP16_MFMA.  In FP16 with gains, each input's
+ *       weights are divided by 2^e, e = ceil(log2 |gain|), and its samples
+ *       multiplied by 2^e at conversion (a power of two: exact), so the FP16
+ *       weights keep full precision; for LP_CI16 only factors below 1 move to
+ *       the samples (32767 * 2 would leave the FP16 range) and the weights
+ *       keep the rest (|w| <= 256).  Gains must be 0 or of magnitude in
+ *       (2^-15, 2^8], else LP_EINVAL.  int8 and |int16| <= 2048 convert to
+ *       FP16 exactly.
  * Requires n_st * n_pol <= 128, n_beams <= 64 per call, n_t % 128 == 0, and
  * a time row (n_st * n_pol complex samples) a multiple of 4 bytes; with
  * LP_FP16_MFMA a row of at most 256 bytes (int16 samples: n_st * n_pol
@@ -239,14 +266,23 @@ lp_status lp_synthesize(lp_ctx *ctx, const lp_band *band, const void *d,
                         void *hip_stream);
 
 /* Trigger rules over one block's candidates (paper Sec. 2: the trigger that
- * reads out the transient buffers).
- *   out      : device lp_trig[cap], ordered by (beam, sample).
+ * reads out the transient buffers).  Every run of every series is kept and
+ * merged, so the list equals the rules' full result whatever its length.
+ *   cand     : device, as written by lp_synthesize (series = beam * n_tec +
+ *              trial, n_t frames each).
+ *   frame0   : stream index of the block's first frame (start-up rule).
+ *   out      : device lp_trig[cap], ordered by (beam, sample); only the first
+ *              cap triggers are written.
  *   n_out    : device int32, the true number of triggers (may exceed cap).
  *   snr_out  : device f32 [n_beams][n_tec] peak envelope / sigma, or NULL.
  *   best_tec : device i32 [n_beams] argmax of snr_out (lowest on ties), or
  *              NULL.
  *   sigma_out: device f32 [n_beams][n_tec], or NULL.
- *   work     : device scratch of lp_trigger_work_bytes(n_beams, n_tec).   */
+ *   work     : device scratch of lp_trigger_work_bytes(n_beams, n_tec, n_t),
+ *              16-byte aligned; no state is kept in it between calls.
+ * Requires n_t a positive multiple of LP_HOP up to 2^20, n_tec <= 4096,
+ * n_beams * n_tec <= 65535 and n_beams * n_tec * n_t / 2 < 2^31; else
+ * LP_EINVAL.                                                               */
 lp_status lp_trigger(lp_ctx *ctx, const void *cand, int32_t n_beams,
                      int32_t n_tec, int64_t n_t, int64_t frame0,
                      float k_sigma, lp_trig *out, int32_t cap, int32_t *n_out,

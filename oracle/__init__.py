@@ -291,6 +291,8 @@ class Stream:
     beta: float = 9.0
     k_sigma: float = 6.0
     gain: np.ndarray | None = None
+    series_group: int = 0          # synthesise this many series at a time
+    keep_z: bool = True            # return the analytic series
     frame0: int = 0
     h: np.ndarray = field(init=False)
     tail: np.ndarray = field(init=False)
@@ -315,8 +317,25 @@ class Stream:
         y = beamform(self.enu, self.n_pol, self.k, self.az_el, x, self.f0,
                      self.fs, gain=self.gain)
         d = dedisperse(self.k, self.tec, y, self.tail, self.f0, self.fs)
-        z = synthesize(self.h, self.k, d.reshape(B * J, S, n_t), self.hist)
-        sigma, wmax, warg = detect(z, n_t, self.frame0, self.warm)
+        # Series are independent from here to the trigger: synthesise and
+        # detect a group at a time (only memory changes with the group).
+        ns = B * J
+        dq = d.reshape(ns, S, n_t)
+        g = self.series_group or ns
+        zs = []
+        sigma = np.zeros(ns)
+        wmax = np.zeros((ns, n_t))
+        warg = np.zeros((ns, n_t), dtype=np.int64)
+        for q0 in range(0, ns, g):
+            q1 = min(ns, q0 + g)
+            hq = np.ascontiguousarray(self.hist[q0:q1])
+            zq = synthesize(self.h, self.k, dq[q0:q1], hq)
+            self.hist[q0:q1] = hq
+            sigma[q0:q1], wmax[q0:q1], warg[q0:q1] = detect(
+                zq, n_t, self.frame0, self.warm)
+            if self.keep_z:
+                zs.append(zq)
+        z = np.concatenate(zs) if self.keep_z else None
         trig, snr_peak, best = trigger(sigma, wmax, warg, B, J, n_t,
                                        self.frame0, self.warm, self.k_sigma)
         self.frame0 += n_t

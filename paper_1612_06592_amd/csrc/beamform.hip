@@ -376,12 +376,15 @@ static void put(std::vector<uint8_t> &v, const T &x) {
 }
 
 lp_status get_bf_plan(lp_ctx *ctx, const lp_array *a, const lp_band *band,
-                      const lp_dir *beams, int n_beams, int prec,
-                      BfPlan **out, const int *st_group,
-                      const int *beam_group) {
+                      const lp_dir *beams, int n_beams, int prec, int dtype,
+                      hipStream_t st, PlanRef<BfPlan> &out,
+                      const int *st_group, const int *beam_group) {
   const int n_in = a->n_st * a->n_pol;
-  std::vector<uint8_t> key;
+  const bool fp16_gain = a->gain && prec == LP_FP16_MFMA;
+  std::vector<uint8_t> key(1, kPlanBf);
   put(key, prec);
+  // The sample type matters only where gains set the FP16 input scaling.
+  put(key, fp16_gain ? dtype : 0);
   put(key, (int)(st_group != nullptr));
   if (st_group) {
     for (int i = 0; i < a->n_st; ++i) put(key, st_group[i]);
@@ -402,12 +405,41 @@ lp_status get_bf_plan(lp_ctx *ctx, const lp_array *a, const lp_band *band,
     put(key, beams[b].az_rad);
     put(key, beams[b].el_rad);
   }
-  std::lock_guard<std::mutex> g(ctx->mu);
-  for (auto &p : ctx->bf)
-    if (p->key == key) {
-      *out = p.get();
-      return LP_OK;
+
+  // Per-input power-of-two scale (FP16 path with gains): e = ceil(log2
+  // |a|); the weights are divided by 2^e (|w| <= 1, full FP16 precision,
+  // never subnormal) and the samples multiplied by 2^e at conversion
+  // (exact).  int8 samples stay within FP16 range for e <= 8 (127 * 2^8).
+  // int16 samples would not for any e > 0 (32767 * 2 > 65504), so for them
+  // the factor above 1 stays in the weights (|w| <= 2^e <= 256) and only
+  // factors below 1 move to the samples.
+  std::vector<double> wscale(n_in, 1.0);
+  std::vector<_Float16> xscale((size_t)((2 * n_in + 15) / 16) * 16,
+                               (_Float16)1.0f);
+  bool scaled = false;
+  if (fp16_gain) {
+    for (int i = 0; i < n_in; ++i) {
+      double mag = std::fabs((double)a->gain[i]);
+      int e = 0;
+      if (mag > 0) e = (int)std::ceil(std::log2(mag));
+      if (e < -14 || e > 8)
+        return set_error(LP_EINVAL,
+                         "gain %g of input %d outside the FP16 scaling range "
+                         "(2^-14 .. 2^8 in magnitude, or 0)",
+                         (double)a->gain[i], i);
+      const int ex = dtype == LP_CI16 ? std::min(e, 0) : e;
+      if (ex != 0) scaled = true;
+      wscale[i] = std::ldexp(1.0, -ex);
+      xscale[2 * i] = xscale[2 * i + 1] = (_Float16)std::ldexp(1.0, ex);
     }
+  }
+
+  std::lock_guard<std::mutex> g(ctx->mu);
+  out.ctx = ctx;
+  if (PlanBase *f = plan_find(ctx, key)) {
+    out.p = static_cast<BfPlan *>(f);
+    return LP_OK;
+  }
   auto p = std::make_unique<BfPlan>();
   p->key = key;
   p->prec = prec;
@@ -416,76 +448,68 @@ lp_status get_bf_plan(lp_ctx *ctx, const lp_array *a, const lp_band *band,
   p->n_sb = band->n_sb;
   p->KS = (2 * n_in + 15) / 16;
   p->NT = (2 * n_beams + 15) / 16;
+  p->scaled = scaled;
 
-  // Per-input power-of-two scale: weights divided by 2^e (|w| <= 1 in
-  // FP16), samples multiplied by 2^e at conversion (exact).
-  std::vector<double> wscale(n_in, 1.0);
-  std::vector<_Float16> xscale((size_t)p->KS * 16, (_Float16)1.0f);
-  if (a->gain && prec == LP_FP16_MFMA) {
-    for (int i = 0; i < n_in; ++i) {
-      double mag = std::fabs((double)a->gain[i]);
-      int e = 0;
-      if (mag > 0) e = (int)std::ceil(std::log2(mag));
-      if (e < -14 || e > 8)
-        return set_error(LP_EINVAL, "gain %g out of the FP16 scaling range",
-                         mag);
-      if (e != 0) p->scaled = true;
-      wscale[i] = std::ldexp(1.0, -e);
-      xscale[2 * i] = xscale[2 * i + 1] = (_Float16)std::ldexp(1.0, e);
-    }
-  }
-  DevBuf denu, dazel, dgain, dws, dk;
+  // Descriptor copies for the weight kernel, one upload: enu, az/el,
+  // weight scale (f64), then subband ids, gains, groups (32-bit).
   std::vector<double> azel(2 * n_beams);
   for (int b = 0; b < n_beams; ++b) {
     azel[2 * b] = beams[b].az_rad;
     azel[2 * b + 1] = beams[b].el_rad;
   }
-  LP_HIP(hipMalloc(&denu.p, 3 * a->n_st * 8));
-  LP_HIP(hipMalloc(&dazel.p, 2 * n_beams * 8));
-  LP_HIP(hipMalloc(&dws.p, n_in * 8));
-  LP_HIP(hipMalloc(&dk.p, band->n_sb * 4));
-  LP_HIP(hipMemcpy(denu.p, a->enu_m, 3 * a->n_st * 8, hipMemcpyHostToDevice));
-  LP_HIP(hipMemcpy(dazel.p, azel.data(), 2 * n_beams * 8, hipMemcpyHostToDevice));
-  LP_HIP(hipMemcpy(dws.p, wscale.data(), n_in * 8, hipMemcpyHostToDevice));
-  LP_HIP(hipMemcpy(dk.p, band->k, band->n_sb * 4, hipMemcpyHostToDevice));
-  if (a->gain) {
-    LP_HIP(hipMalloc(&dgain.p, n_in * 4));
-    LP_HIP(hipMemcpy(dgain.p, a->gain, n_in * 4, hipMemcpyHostToDevice));
-  }
-  DevBuf dsg, dbg;
+  size_t o_enu = 0, o_azel = o_enu + 24 * (size_t)a->n_st,
+         o_ws = o_azel + 16 * (size_t)n_beams, o_k = o_ws + 8 * (size_t)n_in,
+         o_gain = o_k + 4 * (size_t)band->n_sb,
+         o_sg = o_gain + (a->gain ? 4 * (size_t)n_in : 0),
+         o_bg = o_sg + (st_group ? 4 * (size_t)a->n_st : 0),
+         o_end = o_bg + (st_group ? 4 * (size_t)n_beams : 0);
+  std::vector<uint8_t> prm(o_end);
+  std::memcpy(prm.data() + o_enu, a->enu_m, 24 * (size_t)a->n_st);
+  std::memcpy(prm.data() + o_azel, azel.data(), 16 * (size_t)n_beams);
+  std::memcpy(prm.data() + o_ws, wscale.data(), 8 * (size_t)n_in);
+  std::memcpy(prm.data() + o_k, band->k, 4 * (size_t)band->n_sb);
+  if (a->gain) std::memcpy(prm.data() + o_gain, a->gain, 4 * (size_t)n_in);
   if (st_group) {
-    LP_HIP(hipMalloc(&dsg.p, a->n_st * 4));
-    LP_HIP(hipMalloc(&dbg.p, n_beams * 4));
-    LP_HIP(hipMemcpy(dsg.p, st_group, a->n_st * 4, hipMemcpyHostToDevice));
-    LP_HIP(hipMemcpy(dbg.p, beam_group, n_beams * 4, hipMemcpyHostToDevice));
+    std::memcpy(prm.data() + o_sg, st_group, 4 * (size_t)a->n_st);
+    std::memcpy(prm.data() + o_bg, beam_group, 4 * (size_t)n_beams);
   }
+  lp_status rc;
+  if ((rc = plan_alloc(ctx, p.get(), p->params, prm.size())) ||
+      (rc = plan_upload(p.get(), p->params, prm.data(), prm.size(), st)))
+    return rc;
+  const char *P = p->params.as<const char>();
+  const double *denu = reinterpret_cast<const double *>(P + o_enu);
+  const double *dazel = reinterpret_cast<const double *>(P + o_azel);
+  const double *dws = reinterpret_cast<const double *>(P + o_ws);
+  const int *dk = reinterpret_cast<const int *>(P + o_k);
+  const float *dgain =
+      a->gain ? reinterpret_cast<const float *>(P + o_gain) : nullptr;
+  const int *dsg = st_group ? reinterpret_cast<const int *>(P + o_sg) : nullptr;
+  const int *dbg = st_group ? reinterpret_cast<const int *>(P + o_bg) : nullptr;
   double df = band->fs_hz / kM;
   if (prec == LP_FP16_MFMA) {
     long n = (long)band->n_sb * p->NT * p->KS * 256;
-    LP_HIP(hipMalloc(&p->w.p, n * 2));
-    LP_HIP(hipMalloc(&p->xscale.p, xscale.size() * 2));
-    LP_HIP(hipMemcpy(p->xscale.p, xscale.data(), xscale.size() * 2,
-                     hipMemcpyHostToDevice));
+    if ((rc = plan_alloc(ctx, p.get(), p->w, n * 2)) ||
+        (rc = plan_alloc(ctx, p.get(), p->xscale, xscale.size() * 2)) ||
+        (rc = plan_upload(p.get(), p->xscale, xscale.data(), xscale.size() * 2,
+                          st)))
+      return rc;
     hipLaunchKernelGGL(bf_weights_mfma_kernel, dim3((n + 255) / 256),
-                       dim3(256), 0, 0, denu.as<double>(), dazel.as<double>(),
-                       dgain.as<float>(), dws.as<double>(), dk.as<int>(),
+                       dim3(256), 0, st, denu, dazel, dgain, dws, dk,
                        band->f0_hz, df, a->n_pol, n_in, n_beams, band->n_sb,
-                       p->KS, p->NT, dsg.as<const int>(), dbg.as<const int>(),
-                       p->w.as<_Float16>());
+                       p->KS, p->NT, dsg, dbg, p->w.as<_Float16>());
   } else {
     long n = (long)band->n_sb * n_in * n_beams;
-    LP_HIP(hipMalloc(&p->w.p, n * 8));
+    if ((rc = plan_alloc(ctx, p.get(), p->w, n * 8))) return rc;
     hipLaunchKernelGGL(bf_weights_fp32_kernel, dim3((n + 255) / 256),
-                       dim3(256), 0, 0, denu.as<double>(), dazel.as<double>(),
-                       dgain.as<float>(), dws.as<double>(), dk.as<int>(),
+                       dim3(256), 0, st, denu, dazel, dgain, dws, dk,
                        band->f0_hz, df, a->n_pol, n_in, n_beams, band->n_sb,
-                       dsg.as<const int>(), dbg.as<const int>(),
-                       p->w.as<float2>());
+                       dsg, dbg, p->w.as<float2>());
   }
   LP_HIP(hipGetLastError());
-  LP_HIP(hipDeviceSynchronize());
-  *out = p.get();
-  ctx->bf.push_back(std::move(p));
+  BfPlan *raw = p.get();
+  if ((rc = plan_insert(ctx, std::move(p), st))) return rc;
+  out.p = raw;
   return LP_OK;
 }
 
@@ -622,15 +646,18 @@ extern "C" lp_status lp_beamform(lp_ctx *ctx, const lp_array *array,
   if (reinterpret_cast<uintptr_t>(x) % 16 || reinterpret_cast<uintptr_t>(y) % 16)
     return set_error(LP_EINVAL, "lp_beamform: x and y must be 16-byte aligned");
   if ((rc = set_device(ctx))) return rc;
-  BfPlan *p = nullptr;
-  if ((rc = get_bf_plan(ctx, array, band, beams, n_beams, prec, &p))) return rc;
-  return bf_launch(p, x, dtype, n_t, 0, n_t, band->n_sb, y,
-                   static_cast<hipStream_t>(hip_stream));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  PlanRef<BfPlan> p;
+  if ((rc = get_bf_plan(ctx, array, band, beams, n_beams, prec, dtype, st, p)))
+    return rc;
+  return bf_launch(p.get(), x, dtype, n_t, 0, n_t, band->n_sb, y, st);
 }
 
 namespace lp {
-lp_status bf_launch(const BfPlan *p, const void *x, int dtype, long x_nt,
+lp_status bf_launch(BfPlan *p, const void *x, int dtype, long x_nt,
                     long x_t0, long n_t, int n_sb, void *y, hipStream_t st) {
+  lp_status rc;
+  if ((rc = plan_wait(p, st))) return rc;
   if (dtype == LP_CI8)
     return launch_bf<int8_t>(p, static_cast<const int8_t *>(x) +
                                     x_t0 * 2 * p->n_in,

@@ -61,6 +61,101 @@ static void put_band(std::vector<uint8_t> &v, const lp_band *b) {
   put(v, b->fs_hz);
 }
 
+// ----------------------------------------------------------- plan cache
+
+PlanBase *plan_find(lp_ctx *ctx, const std::vector<uint8_t> &key) {
+  for (auto &p : ctx->plans)
+    if (p->key == key) {
+      p->tick = ++ctx->tick;
+      ++p->refs;
+      return p.get();
+    }
+  return nullptr;
+}
+
+// Frees the least recently used plan nobody holds; false if there is none.
+// Its tables may still be read by queued kernels (or, in the bound buffer,
+// be handed to a new plan at once), so the first eviction of a call waits
+// for the device.
+static bool evict_one(lp_ctx *ctx, bool *synced) {
+  auto victim = ctx->plans.end();
+  for (auto it = ctx->plans.begin(); it != ctx->plans.end(); ++it)
+    if ((*it)->refs == 0 &&
+        (victim == ctx->plans.end() || (*it)->tick < (*victim)->tick))
+      victim = it;
+  if (victim == ctx->plans.end()) return false;
+  if (!*synced) {
+    (void)hipDeviceSynchronize();
+    *synced = true;
+  }
+  ctx->plans.erase(victim);
+  return true;
+}
+
+lp_status plan_alloc(lp_ctx *ctx, PlanBase *p, DevBuf &b, size_t n) {
+  n = std::max<size_t>(n, 1);
+  if (!ctx->bound) {
+    LP_HIP(hipMalloc(&b.p, n));
+    b.n = n;
+    p->bytes += n;
+    return LP_OK;
+  }
+  size_t off = 0;
+  bool synced = false;
+  while (!ctx->const_arena.alloc(n, &off))
+    if (!evict_one(ctx, &synced))
+      return set_error(LP_ENOMEM,
+                       "constant buffer: %zu bytes do not fit (%zu free, "
+                       "the rest held by plans in use)",
+                       n, ctx->const_arena.free_bytes());
+  b.p = ctx->const_base + off;
+  b.n = n;
+  b.arena = &ctx->const_arena;
+  b.off = off;
+  p->bytes += Arena::round(n);
+  return LP_OK;
+}
+
+lp_status plan_upload(PlanBase *p, DevBuf &b, const void *src, size_t n,
+                      hipStream_t st) {
+  const uint8_t *s8 = static_cast<const uint8_t *>(src);
+  p->host.emplace_back(s8, s8 + n);
+  LP_HIP(hipMemcpyAsync(b.p, p->host.back().data(), n, hipMemcpyHostToDevice,
+                        st));
+  return LP_OK;
+}
+
+lp_status plan_insert(lp_ctx *ctx, std::unique_ptr<PlanBase> p,
+                      hipStream_t st) {
+  LP_HIP(hipEventCreateWithFlags(&p->ready, hipEventDisableTiming));
+  LP_HIP(hipEventRecord(p->ready, st));
+  p->made_on = st;
+  p->refs = 1;
+  p->tick = ++ctx->tick;
+  ctx->plans.push_back(std::move(p));
+  bool synced = false;
+  while (ctx->plans.size() > ctx->plan_max && evict_one(ctx, &synced)) {
+  }
+  return LP_OK;
+}
+
+lp_status plan_wait(PlanBase *p, hipStream_t st) {
+  if (p->ready_seen.load(std::memory_order_acquire)) return LP_OK;
+  hipError_t e = hipEventQuery(p->ready);
+  if (e == hipSuccess) {
+    p->ready_seen.store(true, std::memory_order_release);
+    return LP_OK;
+  }
+  if (e != hipErrorNotReady) return hip_fail(e, "hipEventQuery(plan)");
+  LP_HIP(hipStreamWaitEvent(st, p->ready, 0));
+  return LP_OK;
+}
+
+void plan_release(lp_ctx *ctx, PlanBase *p) {
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (p->refs > 0) --p->refs;
+}
+
 // ---------------------------------------------------------------- chirp
 
 // kappa = K_ion * 1e16 / c in s^-1 per TECU, K_ion = e^2/(8 pi^2 eps0 m_e)
@@ -105,46 +200,51 @@ __global__ void dd_ratio_kernel(const int *__restrict__ k, int n_sb, double f0,
 }
 
 lp_status get_dd_plan(lp_ctx *ctx, const lp_band *band, const double *tec,
-                      int n_tec, DdPlan **out) {
-  std::vector<uint8_t> key;
+                      int n_tec, hipStream_t st, PlanRef<DdPlan> &out) {
+  std::vector<uint8_t> key(1, kPlanDd);
   put_band(key, band);
   put(key, n_tec);
   for (int j = 0; j < n_tec; ++j) put(key, tec[j]);
   std::lock_guard<std::mutex> g(ctx->mu);
-  for (auto &p : ctx->dd)
-    if (p->key == key) {
-      *out = p.get();
-      return LP_OK;
-    }
+  out.ctx = ctx;
+  if (PlanBase *f = plan_find(ctx, key)) {
+    out.p = static_cast<DdPlan *>(f);
+    return LP_OK;
+  }
   auto p = std::make_unique<DdPlan>();
   p->key = key;
   p->n_tec = n_tec;
   p->n_sb = band->n_sb;
-  size_t js = (size_t)n_tec * band->n_sb;
-  LP_HIP(hipMalloc(&p->base.p, js * 4));
-  LP_HIP(hipMalloc(&p->afac.p, js * 4));
-  LP_HIP(hipMalloc(&p->rfk.p, band->n_sb * 4));
-  LP_HIP(hipMalloc(&p->gq.p, (size_t)band->n_sb * kNfft * 4));
-  DevBuf dtec, dk;
-  LP_HIP(hipMalloc(&dtec.p, n_tec * 8));
-  LP_HIP(hipMalloc(&dk.p, band->n_sb * 4));
-  LP_HIP(hipMemcpy(dtec.p, tec, n_tec * 8, hipMemcpyHostToDevice));
-  LP_HIP(hipMemcpy(dk.p, band->k, band->n_sb * 4, hipMemcpyHostToDevice));
+  const int S = band->n_sb;
+  const size_t js = (size_t)n_tec * S;
+  std::vector<uint8_t> prm((size_t)n_tec * 8 + (size_t)S * 4);
+  std::memcpy(prm.data(), tec, (size_t)n_tec * 8);
+  std::memcpy(prm.data() + (size_t)n_tec * 8, band->k, (size_t)S * 4);
+  lp_status rc;
+  if ((rc = plan_alloc(ctx, p.get(), p->params, prm.size())) ||
+      (rc = plan_upload(p.get(), p->params, prm.data(), prm.size(), st)) ||
+      (rc = plan_alloc(ctx, p.get(), p->base, js * 4)) ||
+      (rc = plan_alloc(ctx, p.get(), p->afac, js * 4)) ||
+      (rc = plan_alloc(ctx, p.get(), p->rfk, (size_t)S * 4)) ||
+      (rc = plan_alloc(ctx, p.get(), p->gq, (size_t)S * kNfft * 4)))
+    return rc;
+  const double *dtec = p->params.as<const double>();
+  const int *dk = reinterpret_cast<const int *>(p->params.as<const char>() +
+                                                (size_t)n_tec * 8);
   int n = (int)js;
   hipLaunchKernelGGL(dd_consts_kernel, dim3((n + 255) / 256), dim3(256), 0,
-                     0, dtec.as<double>(), dk.as<int>(), n_tec, band->n_sb,
-                     band->f0_hz, band->fs_hz / kM, kappa_per_tecu(),
-                     p->base.as<float>(), p->afac.as<float>(),
-                     p->rfk.as<float>());
+                     st, dtec, dk, n_tec, S, band->f0_hz, band->fs_hz / kM,
+                     kappa_per_tecu(), p->base.as<float>(),
+                     p->afac.as<float>(), p->rfk.as<float>());
   LP_HIP(hipGetLastError());
-  const long ng = (long)band->n_sb * kNfft;
+  const long ng = (long)S * kNfft;
   hipLaunchKernelGGL(dd_ratio_kernel, dim3((unsigned)((ng + 255) / 256)),
-                     dim3(256), 0, 0, dk.as<int>(), band->n_sb, band->f0_hz,
-                     band->fs_hz / kM, p->gq.as<float>());
+                     dim3(256), 0, st, dk, S, band->f0_hz, band->fs_hz / kM,
+                     p->gq.as<float>());
   LP_HIP(hipGetLastError());
-  LP_HIP(hipDeviceSynchronize());
-  *out = p.get();
-  ctx->dd.push_back(std::move(p));
+  DdPlan *raw = p.get();
+  if ((rc = plan_insert(ctx, std::move(p), st))) return rc;
+  out.p = raw;
   return LP_OK;
 }
 
@@ -160,17 +260,18 @@ static double bessel_i0(double x) {
   return sum;
 }
 
-lp_status get_syn_plan(lp_ctx *ctx, const lp_band *band, SynPlan **out) {
-  std::vector<uint8_t> key;
+lp_status get_syn_plan(lp_ctx *ctx, const lp_band *band, hipStream_t st,
+                       PlanRef<SynPlan> &out) {
+  std::vector<uint8_t> key(1, kPlanSyn);
   put(key, band->kaiser_beta);
   put(key, band->n_sb);
   for (int i = 0; i < band->n_sb; ++i) put(key, band->k[i]);
   std::lock_guard<std::mutex> g(ctx->mu);
-  for (auto &p : ctx->syn)
-    if (p->key == key) {
-      *out = p.get();
-      return LP_OK;
-    }
+  out.ctx = ctx;
+  if (PlanBase *f = plan_find(ctx, key)) {
+    out.p = static_cast<SynPlan *>(f);
+    return LP_OK;
+  }
   auto p = std::make_unique<SynPlan>();
   p->key = key;
   // Prototype h (Kaiser-windowed sinc, unit sum) in FP64; taps g = M h.
@@ -185,25 +286,30 @@ lp_status get_syn_plan(lp_ctx *ctx, const lp_band *band, SynPlan **out) {
     h[l] = w * sc;
     sum += h[l];
   }
-  std::vector<float> g32(L);
-  for (int l = 0; l < L; ++l) g32[l] = (float)(kM * h[l] / sum);
+  std::vector<float> g32(L), g2(L);
+  for (int l = 0; l < L; ++l) {
+    g32[l] = (float)(kM * h[l] / sum);
+    g2[l] = 2.f * g32[l];
+  }
   std::vector<int16_t> bm(512, -1);
   for (int i = 0; i < band->n_sb; ++i) bm[band->k[i]] = (int16_t)i;
   p->kmax = 0;
   for (int i = 0; i < band->n_sb; ++i) p->kmax = std::max(p->kmax, (int)band->k[i]);
-  LP_HIP(hipMalloc(&p->taps.p, L * 4));
-  LP_HIP(hipMalloc(&p->binmap.p, 512 * 2));
-  LP_HIP(hipMemcpy(p->taps.p, g32.data(), L * 4, hipMemcpyHostToDevice));
-  for (int l = 0; l < L; ++l) g32[l] *= 2.f;
-  LP_HIP(hipMalloc(&p->taps2.p, L * 4));
-  LP_HIP(hipMemcpy(p->taps2.p, g32.data(), L * 4, hipMemcpyHostToDevice));
-  LP_HIP(hipMemcpy(p->binmap.p, bm.data(), 512 * 2, hipMemcpyHostToDevice));
   std::vector<int16_t> kb(band->n_sb);
   for (int i = 0; i < band->n_sb; ++i) kb[i] = (int16_t)band->k[i];
-  LP_HIP(hipMalloc(&p->kbin.p, band->n_sb * 2));
-  LP_HIP(hipMemcpy(p->kbin.p, kb.data(), band->n_sb * 2, hipMemcpyHostToDevice));
-  *out = p.get();
-  ctx->syn.push_back(std::move(p));
+  lp_status rc;
+  if ((rc = plan_alloc(ctx, p.get(), p->taps, L * 4)) ||
+      (rc = plan_upload(p.get(), p->taps, g32.data(), L * 4, st)) ||
+      (rc = plan_alloc(ctx, p.get(), p->taps2, L * 4)) ||
+      (rc = plan_upload(p.get(), p->taps2, g2.data(), L * 4, st)) ||
+      (rc = plan_alloc(ctx, p.get(), p->binmap, 512 * 2)) ||
+      (rc = plan_upload(p.get(), p->binmap, bm.data(), 512 * 2, st)) ||
+      (rc = plan_alloc(ctx, p.get(), p->kbin, band->n_sb * 2)) ||
+      (rc = plan_upload(p.get(), p->kbin, kb.data(), band->n_sb * 2, st)))
+    return rc;
+  SynPlan *raw = p.get();
+  if ((rc = plan_insert(ctx, std::move(p), st))) return rc;
+  out.p = raw;
   return LP_OK;
 }
 
@@ -243,6 +349,57 @@ lp_status lp_ctx_create(int32_t hip_device, lp_ctx **out) {
   return LP_OK;
 }
 
+lp_status lp_ctx_bind_const(lp_ctx *ctx, void *dev, size_t bytes) {
+  if (!ctx) return set_error(LP_EINVAL, "lp_ctx_bind_const: NULL ctx");
+  if (dev && (bytes < 256 || reinterpret_cast<uintptr_t>(dev) % 256))
+    return set_error(LP_EINVAL, "lp_ctx_bind_const: the buffer must be "
+                                "256-byte aligned and at least 256 bytes");
+  lp_status rc;
+  if ((rc = set_device(ctx))) return rc;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  for (auto &p : ctx->plans)
+    if (p->refs > 0)
+      return set_error(LP_EINVAL, "lp_ctx_bind_const: plans are in use "
+                                  "(open serving streams or calls)");
+  if (!ctx->plans.empty()) {
+    LP_HIP(hipDeviceSynchronize());
+    ctx->plans.clear();
+  }
+  ctx->bound = dev != nullptr;
+  ctx->const_base = static_cast<char *>(dev);
+  ctx->const_arena.init(dev ? bytes : 0);
+  return LP_OK;
+}
+
+lp_status lp_ctx_plan_cache(lp_ctx *ctx, int32_t max_plans) {
+  if (!ctx || max_plans < 0)
+    return set_error(LP_EINVAL, "lp_ctx_plan_cache: bad arguments");
+  lp_status rc;
+  if ((rc = set_device(ctx))) return rc;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->plan_max = (size_t)max_plans;
+  bool synced = false;
+  while (ctx->plans.size() > ctx->plan_max && evict_one(ctx, &synced)) {
+  }
+  return LP_OK;
+}
+
+lp_status lp_ctx_plan_stats(lp_ctx *ctx, int32_t *n_plans, int32_t *n_held,
+                            size_t *device_bytes) {
+  if (!ctx) return set_error(LP_EINVAL, "lp_ctx_plan_stats: NULL ctx");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  int held = 0;
+  size_t bytes = 0;
+  for (auto &p : ctx->plans) {
+    held += p->refs > 0;
+    bytes += p->bytes;
+  }
+  if (n_plans) *n_plans = (int32_t)ctx->plans.size();
+  if (n_held) *n_held = held;
+  if (device_bytes) *device_bytes = bytes;
+  return LP_OK;
+}
+
 void lp_ctx_destroy(lp_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
@@ -265,13 +422,6 @@ size_t lp_syn_state_bytes(int32_t n_series, int32_t n_sb) {
 }
 size_t lp_cand_bytes(int32_t n_series, int64_t n_t) {
   return (size_t)n_series * n_t * 8 + (size_t)n_series * (n_t / 16) * 4;
-}
-size_t lp_trigger_work_bytes(int32_t n_beams, int32_t n_tec) {
-  size_t ns = (size_t)n_beams * n_tec;
-  return ns * 16                                   // count, sigma, peak, pad
-         + ns * kTrigPerSeries * 16                // per-series lists
-         + (size_t)n_beams * 16                    // per-beam counts
-         + (size_t)n_beams * n_tec * kTrigPerSeries * sizeof(lp_trig);
 }
 
 }  // extern "C"

@@ -196,17 +196,19 @@ extern "C" lp_status lp_dedisperse(lp_ctx *ctx, const lp_band *band,
   if (flags & ~LP_DD_KEEP_TAIL)
     return set_error(LP_EINVAL, "lp_dedisperse: unknown flags 0x%x", flags);
   if ((rc = set_device(ctx))) return rc;
-  DdPlan *p = nullptr;
-  if ((rc = get_dd_plan(ctx, band, tec_tecu, n_tec, &p))) return rc;
-  return dd_launch(ctx, p, band->n_sb, y, n_beams, n_t, tail,
-                   !(flags & LP_DD_KEEP_TAIL), d,
-                   static_cast<hipStream_t>(hip_stream));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  PlanRef<DdPlan> p;
+  if ((rc = get_dd_plan(ctx, band, tec_tecu, n_tec, st, p))) return rc;
+  return dd_launch(ctx, p.get(), band->n_sb, y, n_beams, n_t, tail,
+                   !(flags & LP_DD_KEEP_TAIL), d, st);
 }
 
 namespace lp {
-lp_status dd_launch(lp_ctx *ctx, const DdPlan *p, int n_sb, const void *y,
+lp_status dd_launch(lp_ctx *ctx, DdPlan *p, int n_sb, const void *y,
                     int n_beams, long n_t, void *tail, bool update_tail,
                     void *d, hipStream_t st) {
+  lp_status rc;
+  if ((rc = plan_wait(p, st))) return rc;
   const int n_hop = (int)(n_t / kHop);
   const long nb = (long)n_beams * n_sb * n_hop;
   if (nb > 0x7fffffffL)

@@ -280,9 +280,11 @@ lp_status lp_dedisperse_plain(lp_ctx *ctx, const lp_band *band,
   if (n_tec <= 0 || n_beams <= 0 || n_t <= 0 || n_t % kHop)
     return set_error(LP_EINVAL, "lp_dedisperse_plain: bad sizes");
   if ((rc = set_device(ctx))) return rc;
-  DdPlan *p = nullptr;
-  if ((rc = get_dd_plan(ctx, band, tec_tecu, n_tec, &p))) return rc;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  PlanRef<DdPlan> p;
+  if ((rc = get_dd_plan(ctx, band, tec_tecu, n_tec, st, p)) ||
+      (rc = plan_wait(p.get(), st)))
+    return rc;
   const int S = band->n_sb, n_hop = (int)(n_t / kHop);
   const size_t per_beam = (size_t)S * n_hop * 4096 * 8;
   const int grp = (int)std::min<size_t>(n_beams, work_bytes / (3 * per_beam));
@@ -335,9 +337,10 @@ lp_status lp_synthesize_plain(lp_ctx *ctx, const lp_band *band, const void *d,
   if (n_series <= 0 || n_t <= 0 || n_t % kHop || frame0 < 0)
     return set_error(LP_EINVAL, "lp_synthesize_plain: bad sizes");
   if ((rc = set_device(ctx))) return rc;
-  SynPlan *p = nullptr;
-  if ((rc = get_syn_plan(ctx, band, &p))) return rc;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  PlanRef<SynPlan> p;
+  if ((rc = get_syn_plan(ctx, band, st, p)) || (rc = plan_wait(p.get(), st)))
+    return rc;
   const int S = band->n_sb;
   const size_t nX = (size_t)(n_t + 15) * 1024, nz = (size_t)n_t * 1024;
   const size_t per = nX * 8 * 2 + nz * 16;

@@ -817,9 +817,11 @@ extern "C" lp_status lp_ppf_analyze(lp_ctx *ctx, const lp_band *band,
   if (!aligned(x, 4) || !aligned(y, 8))
     return set_error(LP_EINVAL, "lp_ppf_analyze: misaligned buffer");
   if ((rc = set_device(ctx))) return rc;
-  SynPlan *p = nullptr;
-  if ((rc = get_syn_plan(ctx, band, &p))) return rc;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  PlanRef<SynPlan> p;
+  if ((rc = get_syn_plan(ctx, band, st, p)) ||
+      (rc = plan_wait(p.get(), st)))
+    return rc;
   const long nf = n_frames;
   const int n_fwd = (int)((nf + kPpfWg - 1) / kPpfWg);
   hipLaunchKernelGGL(ppf_fwd_kernel<kFwdAnalyze>, dim3(n_fwd, n_series),
@@ -842,9 +844,11 @@ extern "C" lp_status lp_ppf_adjoint(lp_ctx *ctx, const lp_band *band,
   if (!aligned(x, 4) || !aligned(y, 8))
     return set_error(LP_EINVAL, "lp_ppf_adjoint: misaligned buffer");
   if ((rc = set_device(ctx))) return rc;
-  SynPlan *p = nullptr;
-  if ((rc = get_syn_plan(ctx, band, &p))) return rc;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  PlanRef<SynPlan> p;
+  if ((rc = get_syn_plan(ctx, band, st, p)) ||
+      (rc = plan_wait(p.get(), st)))
+    return rc;
   const long nf = n_frames, F = nf - (kTaps - 1);
   const int n_adj = (int)((F + kPpfWg - 1) / kPpfWg);
   hipLaunchKernelGGL(ppf_adj_kernel<kAdjPlain>, dim3(n_adj, n_series),
@@ -878,9 +882,11 @@ extern "C" lp_status lp_ppf_invert(lp_ctx *ctx, const lp_band *band,
     return set_error(LP_EINVAL, "lp_ppf_invert: work %zu < %zu bytes",
                      work_bytes, L.total);
   if ((rc = set_device(ctx))) return rc;
-  SynPlan *p = nullptr;
-  if ((rc = get_syn_plan(ctx, band, &p))) return rc;
   hipStream_t hs = static_cast<hipStream_t>(hip_stream);
+  PlanRef<SynPlan> p;
+  if ((rc = get_syn_plan(ctx, band, hs, p)) ||
+      (rc = plan_wait(p.get(), hs)))
+    return rc;
   char *w = static_cast<char *>(work);
   LsmrState *st = reinterpret_cast<LsmrState *>(w + L.st);
   float *part = reinterpret_cast<float *>(w + L.part);
@@ -963,9 +969,11 @@ extern "C" lp_status lp_station_ppf(lp_ctx *ctx, const lp_band *band,
       !aligned(work, 4))
     return set_error(LP_EINVAL, "lp_station_ppf: misaligned buffer");
   if ((rc = set_device(ctx))) return rc;
-  SynPlan *p = nullptr;
-  if ((rc = get_syn_plan(ctx, band, &p))) return rc;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  PlanRef<SynPlan> p;
+  if ((rc = get_syn_plan(ctx, band, st, p)) ||
+      (rc = plan_wait(p.get(), st)))
+    return rc;
   const long nf = n_frames + 2 * (kTaps - 1);   // frames of H's output
   const int n_fwd = (int)((nf + kPpfWg - 1) / kPpfWg);
   short2 *stage = static_cast<short2 *>(work);

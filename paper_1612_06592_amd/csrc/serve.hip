@@ -37,46 +37,6 @@ static int64_t now_ns() {
 
 static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
-// First-fit allocator over [0, size).
-struct Arena {
-  size_t size = 0;
-  std::map<size_t, size_t> free_;  // offset -> length
-  void init(size_t n) {
-    size = n;
-    free_.clear();
-    if (n) free_[0] = n;
-  }
-  bool alloc(size_t n, size_t *off) {
-    n = align256(std::max<size_t>(n, 1));
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= n) {
-        *off = it->first;
-        size_t rest = it->second - n, pos = it->first + n;
-        free_.erase(it);
-        if (rest) free_[pos] = rest;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t n) {
-    n = align256(std::max<size_t>(n, 1));
-    auto it = free_.emplace(off, n).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-};
-
 // Completion marker: a HIP event, or a modelled completion time.
 struct Mark {
   hipEvent_t ev = nullptr;
@@ -188,7 +148,7 @@ static BlockLayout block_layout(const lp_stream_cfg *c, int64_t n_t,
   L.cand = o;
   o += align256(lp_cand_bytes(B * J, n_t));
   L.work = o;
-  o += align256(lp_trigger_work_bytes(B, J));
+  o += align256(lp_trigger_work_bytes(B, J, n_t));
   L.trig = o;
   o += align256((size_t)trig_cap * sizeof(lp_trig));
   L.n = o;
@@ -339,16 +299,32 @@ static void push_result(lp_server *s, Stream *st, const Block &b,
   s->cv_results.notify_all();
 }
 
+// Device-side resources of a stream other than its arena space: its HIP
+// stream, pinned result buffers and its holds on the plans.
+static void drop_device_side(lp_server *s, Stream *st) {
+  if (s->sim) return;
+  if (st->hs) (void)hipStreamSynchronize(st->hs);
+  for (auto &m : st->chunk_marks) free_mark(s, m);
+  if (st->hs) (void)hipStreamDestroy(st->hs);
+  st->hs = nullptr;
+  if (st->h_trig) (void)hipHostFree(st->h_trig);
+  if (st->h_snr) (void)hipHostFree(st->h_snr);
+  if (st->h_best) (void)hipHostFree(st->h_best);
+  if (st->h_n) (void)hipHostFree(st->h_n);
+  st->h_trig = nullptr;
+  st->h_snr = nullptr;
+  st->h_best = nullptr;
+  st->h_n = nullptr;
+  if (st->bf) plan_release(s->ctx, st->bf);
+  if (st->dd) plan_release(s->ctx, st->dd);
+  if (st->syn) plan_release(s->ctx, st->syn);
+  st->bf = nullptr;
+  st->dd = nullptr;
+  st->syn = nullptr;
+}
+
 static void release_stream(lp_server *s, Stream *st) {
-  if (!s->sim) {
-    if (st->hs) (void)hipStreamSynchronize(st->hs);
-    for (auto &m : st->chunk_marks) free_mark(s, m);
-    if (st->hs) (void)hipStreamDestroy(st->hs);
-    if (st->h_trig) (void)hipHostFree(st->h_trig);
-    if (st->h_snr) (void)hipHostFree(st->h_snr);
-    if (st->h_best) (void)hipHostFree(st->h_best);
-    if (st->h_n) (void)hipHostFree(st->h_n);
-  }
+  drop_device_side(s, st);
   st->chunk_marks.clear();
   s->arena.release(st->res_off, st->res_bytes);
 }
@@ -501,6 +477,9 @@ static lp_status check_cfg(const lp_stream_cfg *c) {
                      kHop);
   if (!(c->k_sigma > 0.0f))
     return set_error(LP_EINVAL, "stream cfg: k_sigma must be positive");
+  if (check_trigger_args(c->n_beams, c->n_tec, c->max_n_t, 0, c->k_sigma, 0))
+    return set_error(LP_EINVAL, "stream cfg: trigger limits (%s)",
+                     lp_last_error());
   if (c->trig_cap < 0) return set_error(LP_EINVAL, "stream cfg: trig_cap");
   return LP_OK;
 }
@@ -597,45 +576,62 @@ lp_status lp_stream_open(lp_server *srv, const lp_stream_cfg *cfg,
   sizes_of(cfg, srv->chunk_t, &tail, &hist, &y, &d);
   st->res_bytes = tail + hist + y + d;
   if (!srv->sim) {
-    // Plans are created (synchronously) outside the server lock.
+    // The stream's HIP stream first: its plans' tables are written there,
+    // outside the server lock; the stream holds the plans until it closes.
     if ((rc = set_device(srv->ctx))) return rc;
-    if ((rc = get_bf_plan(srv->ctx, &st->array, &st->band, st->beams.data(),
-                          st->n_beams, st->prec, &st->bf)))
-      return rc;
-    if ((rc = get_dd_plan(srv->ctx, &st->band, st->tec.data(), st->n_tec,
-                          &st->dd)))
-      return rc;
-    if ((rc = get_syn_plan(srv->ctx, &st->band, &st->syn))) return rc;
-  }
-  std::unique_lock<std::mutex> lk(srv->mu);
-  if (srv->stop) return set_error(LP_ECLOSED, "server is shutting down");
-  if (!srv->arena.alloc(st->res_bytes, &st->res_off))
-    return set_error(LP_EAGAIN,
-                     "lp_stream_open: %zu resident bytes do not fit the "
-                     "arena now", st->res_bytes);
-  st->tail_off = st->res_off;
-  st->hist_off = st->tail_off + tail;
-  st->y_off = st->hist_off + hist;
-  st->d_off = st->y_off + y;
-  if (!srv->sim) {
-    auto fail = [&](hipError_t e, const char *what) {
-      srv->arena.release(st->res_off, st->res_bytes);
-      return hip_fail(e, what);
-    };
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&st->hs, hipStreamNonBlocking)))
-      return fail(e, "hipStreamCreate");
-    char *A = srv->arena_base;
-    if ((e = hipMemsetAsync(A + st->tail_off, 0, tail + hist, st->hs)) ||
-        (e = hipStreamSynchronize(st->hs)))
-      return fail(e, "hipMemset(state)");
+      return hip_fail(e, "hipStreamCreate");
+    auto undo = [&](lp_status r) {
+      drop_device_side(srv, st.get());
+      return r;
+    };
+    {
+      PlanRef<BfPlan> bf;
+      PlanRef<DdPlan> dd;
+      PlanRef<SynPlan> syn;
+      if ((rc = get_bf_plan(srv->ctx, &st->array, &st->band, st->beams.data(),
+                            st->n_beams, st->prec, st->dtype, st->hs, bf)) ||
+          (rc = get_dd_plan(srv->ctx, &st->band, st->tec.data(), st->n_tec,
+                            st->hs, dd)) ||
+          (rc = get_syn_plan(srv->ctx, &st->band, st->hs, syn)))
+        return undo(rc);
+      st->bf = bf.keep();
+      st->dd = dd.keep();
+      st->syn = syn.keep();
+    }
     if ((e = hipHostMalloc((void **)&st->h_trig,
                            (size_t)st->trig_cap * sizeof(lp_trig))) ||
         (e = hipHostMalloc((void **)&st->h_snr,
                            (size_t)st->n_beams * st->n_tec * 4)) ||
         (e = hipHostMalloc((void **)&st->h_best, (size_t)st->n_beams * 4)) ||
         (e = hipHostMalloc((void **)&st->h_n, 16)))
-      return fail(e, "hipHostMalloc");
+      return undo(hip_fail(e, "hipHostMalloc"));
+  }
+  std::unique_lock<std::mutex> lk(srv->mu);
+  if (srv->stop) {
+    drop_device_side(srv, st.get());
+    return set_error(LP_ECLOSED, "server is shutting down");
+  }
+  if (!srv->arena.alloc(st->res_bytes, &st->res_off)) {
+    drop_device_side(srv, st.get());
+    return set_error(LP_EAGAIN,
+                     "lp_stream_open: %zu resident bytes do not fit the "
+                     "arena now", st->res_bytes);
+  }
+  st->tail_off = st->res_off;
+  st->hist_off = st->tail_off + tail;
+  st->y_off = st->hist_off + hist;
+  st->d_off = st->y_off + y;
+  if (!srv->sim) {
+    hipError_t e;
+    char *A = srv->arena_base;
+    if ((e = hipMemsetAsync(A + st->tail_off, 0, tail + hist, st->hs)) ||
+        (e = hipStreamSynchronize(st->hs))) {
+      srv->arena.release(st->res_off, st->res_bytes);
+      drop_device_side(srv, st.get());
+      return hip_fail(e, "hipMemset(state)");
+    }
   }
   st->id = srv->next_id++;
   *id = st->id;

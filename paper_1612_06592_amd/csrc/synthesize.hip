@@ -353,17 +353,20 @@ extern "C" lp_status lp_synthesize(lp_ctx *ctx, const lp_band *band,
                      (long long)n_t, kHop);
   if (frame0 < 0) return set_error(LP_EINVAL, "lp_synthesize: frame0 < 0");
   if ((rc = set_device(ctx))) return rc;
-  SynPlan *p = nullptr;
-  if ((rc = get_syn_plan(ctx, band, &p))) return rc;
-  return syn_launch(ctx, p, band->n_sb, d, n_series, n_t, frame0, hist, x_out,
-                    cand, n_t, 0, static_cast<hipStream_t>(hip_stream));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  PlanRef<SynPlan> p;
+  if ((rc = get_syn_plan(ctx, band, st, p))) return rc;
+  return syn_launch(ctx, p.get(), band->n_sb, d, n_series, n_t, frame0, hist,
+                    x_out, cand, n_t, 0, st);
 }
 
 namespace lp {
-lp_status syn_launch(lp_ctx *ctx, const SynPlan *p, int n_sb, const void *d,
+lp_status syn_launch(lp_ctx *ctx, SynPlan *p, int n_sb, const void *d,
                      int n_series, long n_t, long frame0, void *hist,
                      float *x_out, void *cand, long cand_nt, long cand_t0,
                      hipStream_t st) {
+  lp_status rc;
+  if ((rc = plan_wait(p, st))) return rc;
   // The kernel addresses one series' subbands with 32-bit byte offsets.
   if ((long)n_sb * n_t * 8 >= (1L << 32))
     return set_error(LP_EINVAL, "synthesis: %d subbands x %ld frames too large",

@@ -123,9 +123,9 @@ static lp_status check_groups(const char *who, const lp_array *a,
 static lp_status get_ts_plan(lp_ctx *ctx, const lp_array *a,
                              const lp_groups *gr, const lp_band *band,
                              const lp_dir *prelim, int P, const lp_dir *beams,
-                             int B, TsPlan **out) {
+                             int B, hipStream_t st, PlanRef<TsPlan> &out) {
   const int G = gr->n_groups, S = band->n_sb;
-  std::vector<uint8_t> key;
+  std::vector<uint8_t> key(1, kPlanTs);
   put(key, a->n_st);
   for (int i = 0; i < 3 * a->n_st; ++i) put(key, a->enu_m[i]);
   put(key, G);
@@ -145,11 +145,11 @@ static lp_status get_ts_plan(lp_ctx *ctx, const lp_array *a,
     put(key, beams[i].el_rad);
   }
   std::lock_guard<std::mutex> lk(ctx->mu);
-  for (auto &p : ctx->ts)
-    if (p->key == key) {
-      *out = p.get();
-      return LP_OK;
-    }
+  out.ctx = ctx;
+  if (PlanBase *f = plan_find(ctx, key)) {
+    out.p = static_cast<TsPlan *>(f);
+    return LP_OK;
+  }
   auto p = std::make_unique<TsPlan>();
   p->key = key;
   p->G = G;
@@ -212,16 +212,18 @@ static lp_status get_ts_plan(lp_ctx *ctx, const lp_array *a,
       }
     }
   }
-  LP_HIP(hipMalloc(&p->coef.p, coef.size() * sizeof(float2)));
-  LP_HIP(hipMalloc(&p->order.p, B * 4));
-  LP_HIP(hipMalloc(&p->pstart.p, (P + 1) * 4));
-  LP_HIP(hipMemcpy(p->coef.p, coef.data(), coef.size() * sizeof(float2),
-                   hipMemcpyHostToDevice));
-  LP_HIP(hipMemcpy(p->order.p, order.data(), B * 4, hipMemcpyHostToDevice));
-  LP_HIP(hipMemcpy(p->pstart.p, pstart.data(), (P + 1) * 4,
-                   hipMemcpyHostToDevice));
-  *out = p.get();
-  ctx->ts.push_back(std::move(p));
+  lp_status rc;
+  if ((rc = plan_alloc(ctx, p.get(), p->coef, coef.size() * sizeof(float2))) ||
+      (rc = plan_upload(p.get(), p->coef, coef.data(),
+                        coef.size() * sizeof(float2), st)) ||
+      (rc = plan_alloc(ctx, p.get(), p->order, B * 4)) ||
+      (rc = plan_upload(p.get(), p->order, order.data(), B * 4, st)) ||
+      (rc = plan_alloc(ctx, p.get(), p->pstart, (P + 1) * 4)) ||
+      (rc = plan_upload(p.get(), p->pstart, pstart.data(), (P + 1) * 4, st)))
+    return rc;
+  TsPlan *raw = p.get();
+  if ((rc = plan_insert(ctx, std::move(p), st))) return rc;
+  out.p = raw;
   return LP_OK;
 }
 
@@ -267,12 +269,12 @@ extern "C" lp_status lp_beamform_groups(lp_ctx *ctx, const lp_array *array,
       bgroup[g * P + p] = g;
     }
   if ((rc = set_device(ctx))) return rc;
-  BfPlan *plan = nullptr;
-  if ((rc = get_bf_plan(ctx, array, band, dirs.data(), NB, prec, &plan,
-                        groups->group, bgroup.data())))
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  PlanRef<BfPlan> plan;
+  if ((rc = get_bf_plan(ctx, array, band, dirs.data(), NB, prec, dtype, st,
+                        plan, groups->group, bgroup.data())))
     return rc;
-  return bf_launch(plan, x, dtype, n_t, 0, n_t, band->n_sb, y1,
-                   static_cast<hipStream_t>(hip_stream));
+  return bf_launch(plan.get(), x, dtype, n_t, 0, n_t, band->n_sb, y1, st);
 }
 
 extern "C" lp_status lp_beamform_stage2(lp_ctx *ctx, const lp_array *array,
@@ -299,9 +301,11 @@ extern "C" lp_status lp_beamform_stage2(lp_ctx *ctx, const lp_array *array,
     return set_error(LP_EINVAL,
                      "lp_beamform_stage2: y1 and y must be 8-byte aligned");
   if ((rc = set_device(ctx))) return rc;
-  TsPlan *p = nullptr;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  PlanRef<TsPlan> p;
   if ((rc = get_ts_plan(ctx, array, groups, band, prelim, n_prelim, beams,
-                        n_beams, &p)))
+                        n_beams, st, p)) ||
+      (rc = plan_wait(p.get(), st)))
     return rc;
   const bool two = n_t % 2 == 0 && reinterpret_cast<uintptr_t>(y1) % 16 == 0 &&
                    reinterpret_cast<uintptr_t>(y) % 16 == 0;
@@ -312,8 +316,7 @@ extern "C" lp_status lp_beamform_stage2(lp_ctx *ctx, const lp_array *array,
   auto *kern = p->G > 8 ? ts_stage2_kernel<1, kTsMaxGroups>
                : two    ? ts_stage2_kernel<2, 8>
                         : ts_stage2_kernel<1, 8>;
-  hipLaunchKernelGGL(kern, grid, dim3(kTsThreads), shm,
-                     static_cast<hipStream_t>(hip_stream),
+  hipLaunchKernelGGL(kern, grid, dim3(kTsThreads), shm, st,
                      static_cast<const float2 *>(y1), p->coef.as<const float2>(),
                      p->order.as<const int>(), p->pstart.as<const int>(),
                      p->G, p->P, p->B, band->n_sb, (long)n_t,

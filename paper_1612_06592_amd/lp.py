@@ -115,12 +115,19 @@ def lib():
     L.lp_ctx_create.restype = i32
     L.lp_ctx_destroy.argtypes = [vp]
     L.lp_ctx_destroy.restype = None
+    L.lp_ctx_bind_const.argtypes = [vp, vp, C.c_size_t]
+    L.lp_ctx_plan_cache.argtypes = [vp, i32]
+    L.lp_ctx_plan_stats.argtypes = [vp, C.POINTER(i32), C.POINTER(i32),
+                                    C.POINTER(C.c_size_t)]
+    for name in ("lp_ctx_bind_const", "lp_ctx_plan_cache",
+                 "lp_ctx_plan_stats"):
+        getattr(L, name).restype = i32
     for name, args in [("lp_beam_bytes", [i32, i32, i64]),
                        ("lp_dd_state_bytes", [i32, i32]),
                        ("lp_dd_bytes", [i32, i32, i32, i64]),
                        ("lp_syn_state_bytes", [i32, i32]),
                        ("lp_cand_bytes", [i32, i64]),
-                       ("lp_trigger_work_bytes", [i32, i32])]:
+                       ("lp_trigger_work_bytes", [i32, i32, i64])]:
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = C.c_size_t
@@ -201,6 +208,7 @@ def lib():
 def exported_symbols():
     """Names every build must export (those declared in include/lp.h)."""
     return ["lp_last_error", "lp_version", "lp_ctx_create", "lp_ctx_destroy",
+            "lp_ctx_bind_const", "lp_ctx_plan_cache", "lp_ctx_plan_stats",
             "lp_beam_bytes", "lp_dd_state_bytes", "lp_dd_bytes",
             "lp_syn_state_bytes", "lp_cand_bytes", "lp_trigger_work_bytes",
             "lp_beamform", "lp_dedisperse", "lp_synthesize", "lp_trigger",
@@ -278,6 +286,23 @@ class Ctx:
         if self.h:
             lib().lp_ctx_destroy(self.h)
             self.h = C.c_void_p()
+
+    def bind_const(self, buf=None):
+        """Plan tables from a caller device buffer (None: library memory)."""
+        self._const = buf
+        check(lib().lp_ctx_bind_const(self.h, _ptr(buf),
+                                      0 if buf is None else buf.numel()
+                                      * buf.element_size()))
+
+    def plan_cache(self, max_plans: int):
+        check(lib().lp_ctx_plan_cache(self.h, max_plans))
+
+    def plan_stats(self):
+        """(cached plans, plans in use, device bytes of their tables)."""
+        n, held, nb = C.c_int32(), C.c_int32(), C.c_size_t()
+        check(lib().lp_ctx_plan_stats(self.h, C.byref(n), C.byref(held),
+                                      C.byref(nb)))
+        return n.value, held.value, nb.value
 
     def __del__(self):
         try:
@@ -456,7 +481,7 @@ class Pipeline:
             tail=torch.zeros(nbytes("lp_dd_state_bytes", B, S), **u8),
             hist=torch.zeros(nbytes("lp_syn_state_bytes", B * J, S), **u8),
             cand=buf(nbytes("lp_cand_bytes", B * J, n_t)),
-            work=buf(nbytes("lp_trigger_work_bytes", B, J)),
+            work=buf(nbytes("lp_trigger_work_bytes", B, J, n_t)),
             trig=torch.zeros(self.trig_cap * TRIG_DTYPE.itemsize, **u8),
             n_trig=torch.zeros(1, dtype=torch.int32, device=self.device),
             snr=torch.zeros((B, J), dtype=torch.float32, device=self.device),

@@ -33,7 +33,9 @@ def test_sizing_helpers():
     assert lp.nbytes("lp_dd_bytes", 7, 32, 244, 65536) == 7 * 32 * 244 * 65536 * 8
     assert lp.nbytes("lp_syn_state_bytes", 224, 244) == 224 * 244 * 16 * 8
     assert lp.nbytes("lp_cand_bytes", 2, 4096) == 2 * 4096 * 8 + 2 * 256 * 4
-    assert lp.nbytes("lp_trigger_work_bytes", 1, 1) > 0
+    assert lp.nbytes("lp_trigger_work_bytes", 1, 1, 2048) > 0
+    assert lp.nbytes("lp_trigger_work_bytes", 7, 32, 65536) >= 7 * 32 * 65536 * 8
+    assert lp.nbytes("lp_trigger_work_bytes", 1, 1, 0) == 0
 
 
 def test_version_and_null_ctx_errors():

@@ -6,19 +6,27 @@ import numpy as np
 import pytest
 
 import lofarsim
+from chain import OracleChain, compare_triggers
 from paper_1612_06592_amd import lp
 
 pytestmark = pytest.mark.gpu
 
 
 def make_stream(seed, n_st, rings, k0, n_sb, tec, lens, n_pulses=2,
-                snr=(12.0, 12.0)):
-    """One generated observation cut into consecutive blocks (device)."""
+                snr=(12.0, 12.0), trials=None, dtype="ci8", sigma=8.0):
+    """One generated observation cut into consecutive blocks (device).
+    trials: TEC trial list (default: the true TEC alone)."""
     import torch
+    if trials is None:
+        trials, idx = (tec,), 0
+    else:
+        idx = int(np.argmin(np.abs(np.asarray(trials) - tec)))
     cfg = lofarsim.get_config("c2", n_st=n_st, hex_rings=rings,
                               k=tuple(range(k0, k0 + n_sb)), n_t=sum(lens),
-                              tec=(tec,), true_tec=tec, n_pulses=n_pulses,
-                              snr=snr, seed=(seed,))
+                              tec=tuple(trials), true_tec_index=idx,
+                              true_tec=tec, n_pulses=n_pulses,
+                              snr=snr, seed=(seed,), dtype=dtype,
+                              sigma=sigma)
     blk = lofarsim.generate(cfg)
     blocks, a = [], 0
     for n_t in lens:
@@ -30,9 +38,10 @@ def make_stream(seed, n_st, rings, k0, n_sb, tec, lens, n_pulses=2,
     return blocks
 
 
-def stream_cfg(blk, max_n_t):
+def stream_cfg(blk, max_n_t, prec=lp.LP_FP16_MFMA):
+    dtype = lp.LP_CI8 if blk.x.dtype == np.int8 else lp.LP_CI16
     return lp.StreamCfg(blk.enu, blk.k, blk.az_el, blk.tec, max_n_t,
-                        dtype=lp.LP_CI8, prec=lp.LP_FP16_MFMA, trig_cap=256)
+                        dtype=dtype, prec=prec, trig_cap=256)
 
 
 def direct(blocks):
@@ -60,7 +69,7 @@ def direct(blocks):
     return out
 
 
-def serve(streams, chunk_t=2048, interleave=True):
+def serve(streams, chunk_t=2048, interleave=True, precs=None):
     """Submit every stream's blocks to one server; returns results per
     stream in submission order."""
     import torch
@@ -68,9 +77,10 @@ def serve(streams, chunk_t=2048, interleave=True):
     arena = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
     srv = lp.Server(ctx, arena, arena.numel(), max_slots=8, chunk_t=chunk_t)
     ids = []
-    for blocks in streams:
+    for si, blocks in enumerate(streams):
         max_n_t = max(b.n_t for b, _ in blocks)
-        ids.append(srv.open(stream_cfg(blocks[0][0], max_n_t)))
+        prec = lp.LP_FP16_MFMA if precs is None else precs[si]
+        ids.append(srv.open(stream_cfg(blocks[0][0], max_n_t, prec)))
     order = []
     n_max = max(len(s) for s in streams)
     for i in range(n_max):
@@ -134,3 +144,42 @@ def test_alone_equals_in_the_mix():
           f"p99 {np.percentile(lat, 99):.2f} max {lat.max():.2f}; "
           f"chunks {stats['chunks_issued']}", flush=True)
     assert np.all(lat < dl)
+
+
+def test_served_mix_against_oracle():
+    """Every stream of a concurrent mix against the FP64 oracle's chain run
+    over the same consecutive, uneven blocks (state carried from block to
+    block): per-series peak SNR within the FP16 bound, trigger lists equal
+    (beam exact, sample within 1, decisions within 1 % of the threshold
+    excepted), best trial equal.  The mix has an FP16-MFMA stream, an FP32
+    stream, a 4-trial stream and an int16 stream."""
+    A = make_stream(11, 8, 1, 52, 32, 7.0, [4096, 8192, 2048])
+    B = make_stream(12, 12, 0, 100, 48, 20.0, [8192, 2048, 4096])
+    Cm = make_stream(13, 6, 1, 300, 24, 10.0, [2048, 4096, 2048, 6144],
+                     trials=(0.0, 5.0, 10.0, 15.0), snr=(14.0, 14.0))
+    D = make_stream(14, 4, 0, 200, 20, 3.0, [6144, 2048], dtype="ci16",
+                    sigma=16.0)
+    streams = [A, B, Cm, D]
+    precs = [lp.LP_FP16_MFMA, lp.LP_FP32, lp.LP_FP16_MFMA, lp.LP_FP16_MFMA]
+    tol = {lp.LP_FP16_MFMA: 1e-3, lp.LP_FP32: 1e-5}
+    got, stats = serve(streams, chunk_t=2048, precs=precs)
+    n_trig = 0
+    for si, blocks in enumerate(streams):
+        blk0 = blocks[0][0]
+        oc = OracleChain(blk0)
+        for bi, (blk, _) in enumerate(blocks):
+            o = oc.process(blk.x)
+            g = got[si][bi]
+            label = f"stream {si} block {bi} (n_t {blk.n_t})"
+            snr_g = np.asarray(g["snr"], np.float64).ravel()
+            snr_o = o["snr"].ravel()
+            e = np.max(np.abs(snr_g - snr_o) / np.maximum(snr_o, 1e-30))
+            print(f"{label}: peak-SNR max rel err {e:.2e}, triggers "
+                  f"gpu {len(g['trig'])} oracle {len(o['trig'])}", flush=True)
+            assert e <= 2 * tol[precs[si]], label
+            assert g["n_trig"] == len(g["trig"])
+            miss, extra = compare_triggers(g["trig"], o["trig"], o["sigma"])
+            assert not miss and not extra, (label, miss, extra)
+            assert np.array_equal(np.asarray(g["best_tec"]), o["best"]), label
+            n_trig += len(o["trig"])
+    assert n_trig >= 4
