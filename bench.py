@@ -268,14 +268,15 @@ def main():
                         achieved / FP32_UNPACKED_TFLOPS, 4)}
 
     # Trigger sanity on the last block: the injected pulses are found.
+    # The stream has run 1 + warmup + steps blocks (the error leg's first
+    # block included); the last one starts at this ADC offset.
+    t_last = (a.warmup + a.steps) * cfg.n_t * 1024
     trig = p.triggers()
-    found = sum(any(abs(int(t["sample"]) - (pl["n0"] + (a.warmup + a.steps - 1)
-                                             * cfg.n_t * 1024)) <= 1
+    found = sum(any(abs(int(t["sample"]) - (pl["n0"] + t_last)) <= 1
                     for t in trig) for pl in blk.pulses)
     injected = sorted({int(pl["beam"]) for pl in blk.pulses})
     # Per pulse: the beam of its highest-SNR trigger (a strong pulse's
     # sidelobes also trigger neighbouring beams).
-    t_last = (a.warmup + a.steps - 1) * cfg.n_t * 1024
     best_beam = []
     for pl in blk.pulses:
         near = [t for t in trig
