@@ -289,6 +289,24 @@ lp_status lp_trigger(lp_ctx *ctx, const void *cand, int32_t n_beams,
                      float *snr_out, int32_t *best_tec, float *sigma_out,
                      void *work, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lp_trigger
+ * with its workspace in a fixed device array of LP_TRIGGER_SCRATCH_BYTES
+ * that the library holds on every device it runs on until the process ends
+ * (its address is taken once per device by lp_ctx_create).  Arguments,
+ * limits and results as lp_trigger, minus `work`; the call allocates
+ * nothing.  LP_EINVAL when lp_trigger_work_bytes(n_beams, n_tec, n_t)
+ * exceeds LP_TRIGGER_SCRATCH_BYTES (e.g. 61 beams x 1 trial x 32768 samples
+ * needs 12 MB, 7 x 32 x 65536 needs 88 MB).  All calls on one device share
+ * the array: calls that may overlap on the device (different streams, or
+ * threads without ordering) race and must be serialised by the caller.   */
+#define LP_TRIGGER_SCRATCH_BYTES ((size_t)128 << 20)
+lp_status lp_trigger_noalloc(lp_ctx *ctx, const void *cand, int32_t n_beams,
+                             int32_t n_tec, int64_t n_t, int64_t frame0,
+                             float k_sigma, lp_trig *out, int32_t cap,
+                             int32_t *n_out, float *snr_out, int32_t *best_tec,
+                             float *sigma_out, void *hip_stream);
+
 /* ---- plain FP32 comparator ------------------------------------------- */
 /* The same de-dispersion and synthesis arithmetic organised the
  * straightforward way: every intermediate (overlap-save buffers, spectra,

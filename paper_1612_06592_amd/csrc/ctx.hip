@@ -345,6 +345,8 @@ lp_status lp_ctx_create(int32_t hip_device, lp_ctx **out) {
   LP_HIP(hipMalloc(&ctx->tw4096.p, 4096 * sizeof(float2)));
   LP_HIP(hipMemcpy(ctx->tw4096.p, tw.data(), 4096 * sizeof(float2),
                    hipMemcpyHostToDevice));
+  lp_status rc = trig_scratch_attach(hip_device);
+  if (rc) return rc;
   *out = ctx.release();
   return LP_OK;
 }

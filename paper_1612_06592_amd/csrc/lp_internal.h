@@ -251,6 +251,9 @@ lp_status get_syn_plan(lp_ctx *ctx, const lp_band *band, hipStream_t st,
                        PlanRef<SynPlan> &out);
 lp_status check_band(const lp_band *band);
 lp_status set_device(lp_ctx *ctx);
+// Takes the device address of lp_trigger_noalloc's fixed workspace for
+// `device` (current); once per device, later calls return at once.
+lp_status trig_scratch_attach(int device);
 
 // Stage launches on an explicit stream, without argument checks (the
 // public entry points and the serving loop validate first).

@@ -526,6 +526,70 @@ extern "C" lp_status lp_trigger(lp_ctx *ctx, const void *cand, int32_t n_beams,
                      static_cast<hipStream_t>(hip_stream));
 }
 
+// ---- lp_trigger_noalloc: the workspace in a fixed device array ----------
+// One copy per device, LP_TRIGGER_SCRATCH_BYTES long, held until the process
+// ends.  Host code never passes `scratch` itself to a kernel (on the host the
+// name is only a stand-in): lp_ctx_create takes its device address once per
+// device with hipGetSymbolAddress, and every launch uses that address.
+static __device__ __align__(256) unsigned char scratch[LP_TRIGGER_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+namespace lp {
+// Called by lp_ctx_create with `device` current.
+lp_status trig_scratch_attach(int device) {
+  if (device < 0 || device >= kMaxScratchDevices)
+    return set_error(LP_EINVAL, "device %d beyond the scratch table", device);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[device]) return LP_OK;
+  void *ptr = nullptr;
+  LP_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr || reinterpret_cast<uintptr_t>(ptr) % 256)
+    return set_error(LP_EHIP, "trigger scratch: bad device address %p", ptr);
+  g_scratch_ptr[device] = ptr;
+  return LP_OK;
+}
+}  // namespace lp
+
+extern "C" lp_status lp_trigger_noalloc(lp_ctx *ctx, const void *cand,
+                                        int32_t n_beams, int32_t n_tec,
+                                        int64_t n_t, int64_t frame0,
+                                        float k_sigma, lp_trig *out,
+                                        int32_t cap, int32_t *n_out,
+                                        float *snr_out, int32_t *best_tec,
+                                        float *sigma_out, void *hip_stream) {
+  if (!ctx || !cand || !n_out || (cap > 0 && !out))
+    return set_error(LP_EINVAL, "lp_trigger_noalloc: NULL argument");
+  lp_status rc = check_trigger_args(n_beams, n_tec, n_t, frame0, k_sigma, cap);
+  if (rc) return rc;
+  const size_t need = work_bytes(n_beams, n_tec, n_t);
+  if (need > LP_TRIGGER_SCRATCH_BYTES)
+    return set_error(LP_EINVAL,
+                     "lp_trigger_noalloc: %d beams x %d trials x %lld samples "
+                     "need %zu bytes of workspace, above the fixed %zu",
+                     n_beams, n_tec, (long long)n_t, need,
+                     (size_t)LP_TRIGGER_SCRATCH_BYTES);
+  if ((rc = set_device(ctx))) return rc;
+  void *ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (ctx->device >= 0 && ctx->device < kMaxScratchDevices)
+      ptr = g_scratch_ptr[ctx->device];
+  }
+  if (!ptr)
+    return set_error(LP_EHIP, "lp_trigger_noalloc: no scratch address for "
+                              "device %d", ctx->device);
+  // Every workspace word the kernels read is written earlier in the same
+  // call, so nothing needs clearing between calls.
+  return trig_launch(cand, n_beams, n_tec, n_t, frame0, k_sigma, out, cap,
+                     n_out, snr_out, best_tec, sigma_out, ptr,
+                     static_cast<hipStream_t>(hip_stream));
+}
+
 namespace lp {
 lp_status trig_launch(const void *cand, int n_beams, int n_tec, long n_t,
                       long frame0, float k_sigma, lp_trig *out, int cap,

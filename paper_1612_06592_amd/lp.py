@@ -141,8 +141,10 @@ def lib():
                                 vp, vp, vp, vp]
     L.lp_trigger.argtypes = [vp, vp, i32, i32, i64, i64, f32, vp, i32, vp,
                              vp, vp, vp, vp, vp]
+    L.lp_trigger_noalloc.argtypes = [vp, vp, i32, i32, i64, i64, f32, vp,
+                                     i32, vp, vp, vp, vp, vp]
     for name in ("lp_beamform", "lp_dedisperse", "lp_synthesize",
-                 "lp_trigger"):
+                 "lp_trigger", "lp_trigger_noalloc"):
         getattr(L, name).restype = i32
     L.lp_plain_work_bytes.argtypes = [i32, i32, i32, i64]
     L.lp_plain_work_bytes.restype = C.c_size_t
@@ -212,6 +214,7 @@ def exported_symbols():
             "lp_beam_bytes", "lp_dd_state_bytes", "lp_dd_bytes",
             "lp_syn_state_bytes", "lp_cand_bytes", "lp_trigger_work_bytes",
             "lp_beamform", "lp_dedisperse", "lp_synthesize", "lp_trigger",
+            "lp_trigger_noalloc",
             "lp_plain_work_bytes", "lp_dedisperse_plain",
             "lp_synthesize_plain", "lp_beamform_groups", "lp_beamform_stage2",
             "lp_ppf_analyze", "lp_ppf_adjoint",
@@ -343,6 +346,19 @@ def trigger(ctx: Ctx, cand, n_beams: int, n_tec: int, n_t: int, frame0: int,
                            k_sigma, _ptr(out), cap, _ptr(n_out),
                            _ptr(snr_out), _ptr(best_tec), _ptr(sigma_out),
                            _ptr(work), _stream(stream)))
+
+
+def trigger_noalloc(ctx: Ctx, cand, n_beams: int, n_tec: int, n_t: int,
+                    frame0: int, k_sigma: float, out, cap: int, n_out,
+                    snr_out=None, best_tec=None, sigma_out=None, stream=None):
+    check(lib().lp_trigger_noalloc(ctx.h, _ptr(cand), n_beams, n_tec, n_t,
+                                   frame0, k_sigma, _ptr(out), cap,
+                                   _ptr(n_out), _ptr(snr_out),
+                                   _ptr(best_tec), _ptr(sigma_out),
+                                   _stream(stream)))
+
+
+TRIGGER_SCRATCH_BYTES = 128 << 20   # LP_TRIGGER_SCRATCH_BYTES
 
 
 def dedisperse_plain(ctx: Ctx, band: Band, tec, y, n_beams: int, n_t: int,
