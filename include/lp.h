@@ -259,7 +259,8 @@ lp_status lp_dedisperse(lp_ctx *ctx, const lp_band *band,
  *   x_out  : device f32 [n_series][n_t * LP_M] real series 2 Re z, or NULL.
  *   cand   : device, lp_cand_bytes(n_series, n_t), overwritten.
  * n_t must be a positive multiple of LP_HOP, and one series' input must be
- * below 4 GiB (n_sb * n_t * 8 < 2^32; the kernel uses 32-bit offsets).     */
+ * below 4 GiB with a row to spare ((n_sb + 1) * n_t * 8 < 2^32; the kernel
+ * uses 32-bit offsets).                                                    */
 lp_status lp_synthesize(lp_ctx *ctx, const lp_band *band, const void *d,
                         int32_t n_series, int64_t n_t, int64_t frame0,
                         void *hist, float *x_out, void *cand,

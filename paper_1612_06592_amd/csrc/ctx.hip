@@ -226,7 +226,30 @@ lp_status get_dd_plan(lp_ctx *ctx, const lp_band *band, const double *tec,
       (rc = plan_alloc(ctx, p.get(), p->base, js * 4)) ||
       (rc = plan_alloc(ctx, p.get(), p->afac, js * 4)) ||
       (rc = plan_alloc(ctx, p.get(), p->rfk, (size_t)S * 4)) ||
-      (rc = plan_alloc(ctx, p.get(), p->gq, (size_t)S * kNfft * 4)))
+      (rc = plan_alloc(ctx, p.get(), p->gq, (size_t)S * kNfft * 4)) ||
+      (rc = plan_alloc(ctx, p.get(), p->step, (size_t)2 * S * 4)))
+    return rc;
+  // A uniform grid (at least two trials, T_t = T_0 + t dT) lets the kernel
+  // step the chirp from trial to trial: per subband the step's phase
+  // kappa dT / f_k, range-reduced in FP64.
+  std::vector<float> stp((size_t)2 * S, 0.0f);
+  if (n_tec >= 2) {
+    const double dT = (tec[n_tec - 1] - tec[0]) / (n_tec - 1);
+    bool uni = true;
+    for (int j = 0; j < n_tec; ++j)
+      if (std::fabs(tec[j] - (tec[0] + j * dT)) >
+          1e-9 * std::max(1.0, std::fabs(tec[n_tec - 1])))
+        uni = false;
+    p->uniform = uni;
+    const double kap = kappa_per_tecu(), df = band->fs_hz / kM;
+    for (int s = 0; s < S; ++s) {
+      const double fk = band->f0_hz + (double)band->k[s] * df;
+      const double dA = kap * dT / fk;
+      stp[s] = (float)(dA - std::rint(dA));
+      stp[(size_t)S + s] = (float)dA;
+    }
+  }
+  if ((rc = plan_upload(p.get(), p->step, stp.data(), stp.size() * 4, st)))
     return rc;
   const double *dtec = p->params.as<const double>();
   const int *dk = reinterpret_cast<const int *>(p->params.as<const char>() +

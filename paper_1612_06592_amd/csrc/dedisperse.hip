@@ -8,8 +8,13 @@
 //
 // One 256-thread workgroup per (beam, subband, hop).  Each thread owns 16
 // points; the 4096-point transform is three radix-16 Stockham passes with
-// two exchanges through a padded 34 KB LDS tile.  The forward spectrum
-// stays in registers across all trials.
+// two exchanges through a padded 34 KB LDS tile.  Each thread's base
+// twiddle of a pass comes from two small LDS tables and its powers from a
+// product tree (tables of all powers were measured slower: this kernel is
+// close to bound by LDS instructions as well as VALU).  The forward spectrum stays in registers across all trials; on a uniform trial
+// grid the chirp of trial t + 1 is that of trial t times a fixed per-bin
+// factor, so each trial costs one complex product per bin instead of a
+// sine and a cosine.
 #include <cmath>
 
 #include "fft_dev.h"
@@ -20,15 +25,34 @@ namespace lp {
 constexpr int kDdThreads = 256;
 constexpr int kDdLds = 4096 + 128;  // slot of element 4095 is 4222
 
-// 4096-point transform of v[r] = in[j + 256 r] (j = thread); on return
-// v[r] = out[j + 256 r].  Unnormalised; INV selects exp(+2 pi i ...).
-// Twiddles exp(-2 pi i n / 4096) from two small LDS tables:
-// coarse[c] = w^(16 c) (c < 256), fine[f] = w^f (f < 16).
+// 16-point DFT returning only outputs 8..15 (in v[8..15]; v[0..7] are left
+// undefined): the second radix-4 stage forms just its outputs 2 and 3.
 template <bool INV>
-__device__ __forceinline__ float2 tw4096_lds(const float2 *coarse,
-                                             const float2 *fine, int n) {
-  float2 w = cmul(coarse[(n >> 4) & 255], fine[n & 15]);
-  return INV ? make_float2(w.x, -w.y) : w;
+__device__ __forceinline__ void dft16_hi(float2 *v) {
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+#pragma unroll
+  for (int n2 = 1; n2 < 4; ++n2) {
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1) {
+      float2 w = w16(n2 * k1);
+      v[n2 + 4 * k1] = INV ? cmulc(v[n2 + 4 * k1], w) : cmul(v[n2 + 4 * k1], w);
+    }
+  }
+  float2 o[8];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    const float2 a = v[4 * k1], b = v[4 * k1 + 1], c = v[4 * k1 + 2],
+                 d = v[4 * k1 + 3];
+    const float2 t0 = cadd(a, c), t1 = csub(a, c), t2 = cadd(b, d),
+                 t3 = csub(b, d);
+    o[k1] = csub(t0, t2);  // output k1 + 8
+    // output k1 + 12: t1 + i t3 (forward) or t1 - i t3 (inverse)
+    o[4 + k1] = INV ? make_float2(t1.x + t3.y, t1.y - t3.x)
+                    : make_float2(t1.x - t3.y, t1.y + t3.x);
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[8 + i] = o[i];
 }
 
 // v[r] *= w^r (r = 1..15), the powers formed by a product tree of depth 4
@@ -54,10 +78,19 @@ __device__ __forceinline__ void pow16_twiddle(float2 *v, const float2 w1) {
   v[15] = cmul(v[15], cmul(w8, w7));
 }
 
-template <bool INV>
+// LDS twiddle tables of one workgroup (w = exp(-2 pi i / 4096)):
+//   coarse[c] = w^(16 c) (c < 256), fine[f] = w^f (f < 16).
+struct DdTw {
+  float2 coarse[256];
+  float2 fine[16];
+};
+
+// 4096-point transform of v[r] = in[j + 256 r] (j = thread); on return
+// v[r] = out[j + 256 r] (HI: only r >= 8).  Unnormalised; INV selects
+// exp(+2 pi i ...).
+template <bool INV, bool HI>
 __device__ __forceinline__ void fft4096(float2 *v, float2 *lds,
-                                        const float2 *coarse,
-                                        const float2 *fine, int j) {
+                                        const DdTw &tw, int j) {
   // Element e sits at slot e + e / 32 (one pad slot per 32: every access
   // pattern below puts the 64 lanes' 8-byte words evenly on the banks, for
   // 32 or 64 banks).  In closed form (j < 256, r < 16):
@@ -73,11 +106,11 @@ __device__ __forceinline__ void fft4096(float2 *v, float2 *lds,
     for (int r = 0; r < 16; ++r) lds[b0 + r] = v[r];
   }
   __syncthreads();
-  // Pass 1 (Ns = 16).
+  // Pass 1 (Ns = 16): twiddle w^(16 (j mod 16) r).
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = lds[sj + 264 * r];
   {
-    const float2 w = coarse[j & 15];  // angle 2 pi (j mod 16) / 256
+    const float2 w = tw.coarse[j & 15];
     pow16_twiddle(v, INV ? make_float2(w.x, -w.y) : w);
   }
   dft16<INV>(v);
@@ -88,24 +121,46 @@ __device__ __forceinline__ void fft4096(float2 *v, float2 *lds,
     for (int r = 0; r < 16; ++r) lds[b2 + 16 * r + (r >> 1)] = v[r];
   }
   __syncthreads();
-  // Pass 2 (Ns = 256): output index j + 256 r stays in registers.
+  // Pass 2 (Ns = 256): twiddle w^(j r); output index j + 256 r stays in
+  // registers.
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = lds[sj + 264 * r];
-  pow16_twiddle(v, tw4096_lds<INV>(coarse, fine, j));
-  dft16<INV>(v);
+  {
+    const float2 w = cmul(tw.coarse[j >> 4], tw.fine[j & 15]);
+    pow16_twiddle(v, INV ? make_float2(w.x, -w.y) : w);
+  }
+  if (HI)
+    dft16_hi<INV>(v);
+  else
+    dft16<INV>(v);
 }
 
+// Chirp factor exp(-2 pi i c) for a phase c in cycles, |c| <= 1/2 after the
+// reduction; the hardware sine and cosine take revolutions.
+__device__ __forceinline__ float2 chirp(float c) {
+  c -= rintf(c);
+  return make_float2(__builtin_amdgcn_cosf(c), -__builtin_amdgcn_sinf(c));
+}
+
+// REC: the trials are uniformly spaced (step[0][s] = frac(dA), step[1][s] =
+// dA with dA = kappa dT / f_k), so trial t + 1's chirp is trial t's times
+// exp(-2 pi i (frac(dA) - dA g_q)); the per-bin factor is formed once per
+// hop with the accurate sincospi.
+template <bool REC>
 __global__ __launch_bounds__(kDdThreads)
 __attribute__((amdgpu_waves_per_eu(4, 8))) void dd_kernel(
     const float2 *__restrict__ y, float2 *__restrict__ tail, int update_tail,
     float2 *__restrict__ d, const float2 *__restrict__ tw,
     const float *__restrict__ base, const float *__restrict__ afac,
-    const float *__restrict__ gq, int n_sb, int n_tec, long n_t, int n_hop,
-    long n_blocks) {
+    const float *__restrict__ step, const float *__restrict__ gq, int n_sb,
+    int n_tec, long n_t, int n_hop, long n_blocks) {
   __shared__ float2 lds[kDdLds];
-  __shared__ float2 coarse[256], fine[16];
-  coarse[threadIdx.x] = tw[16 * threadIdx.x];
-  if (threadIdx.x < 16) fine[threadIdx.x] = tw[threadIdx.x];
+  __shared__ DdTw tws;
+  {
+    const int i = threadIdx.x;  // tw[n] = w^n, n < 4096
+    tws.coarse[i] = tw[16 * i];
+    if (i < 16) tws.fine[i] = tw[i];
+  }
   // (the barrier inside the first transform orders these before use)
   const long bid = xcd_remap(blockIdx.x, n_blocks);
   const int h = (int)(bid % n_hop);
@@ -124,7 +179,7 @@ __attribute__((amdgpu_waves_per_eu(4, 8))) void dd_kernel(
 #pragma unroll
   for (int r = 8; r < 16; ++r) v[r] = ys[hs + j + 256 * (r - 8)];
 
-  fft4096<false>(v, lds, coarse, fine, j);
+  fft4096<false, false>(v, lds, tws, j);
 
   // Hop 0 read the old tail above (and every thread has passed the
   // barriers inside the transform), so it can now store the new one.
@@ -133,38 +188,69 @@ __attribute__((amdgpu_waves_per_eu(4, 8))) void dd_kernel(
     for (int r = 0; r < 8; ++r) tl[j + 256 * r] = ys[n_t - kHist + j + 256 * r];
   }
 
+  // The inverse transform's 1 / 4096 applied to the spectrum (a power of
+  // two: exact, so every later rounding is the same as scaling the output).
   float2 U[16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) U[r] = v[r];
+  for (int r = 0; r < 16; ++r)
+    U[r] = make_float2(v[r].x * (1.0f / 4096.0f), v[r].y * (1.0f / 4096.0f));
   // Chirp phase of bin q (signed q_s) for trial t, in cycles:
   //   frac(kappa T / (f_k + nu_q)) + q_s D / 4096
   //     = frac(A) - A g_q + (q_s mod 4) / 4   (mod 1),
   // with A = kappa T / f_k, g_q = x / (1 + x), x = nu_q / f_k from the plan
   // table, and q_s mod 4 = j mod 4 for every bin of thread j.  The residual
-  // A g_q is below ~0.4 cycles; the hardware sine/cosine take revolutions.
+  // A g_q is below ~0.4 cycles.
   const __amdgpu_buffer_rsrc_t grs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float *>(gq), 0, n_sb * kNfft * 4, kRawBufferWord3);
   const float e = 0.25f * (float)(j & 3);
-  const float scale = 1.0f / 4096.0f;
-  for (int jt = 0; jt < n_tec; ++jt) {
-    const int jo = opaque(j);
-    const float bse = base[jt * n_sb + s] + e, A = afac[jt * n_sb + s];
-    const int goff = 4 * (s * kNfft + jo);
+  float2 *outb = d + ((long)b * n_tec * n_sb + s) * n_t + hs + j;
+  const long trial_stride = (long)n_sb * n_t;
+  if (REC) {
+    // U becomes trial 0's chirped spectrum; R the per-trial factor.
+    const float bse = base[s] + e, A = afac[s];
+    const float fdA = step[s], dA = step[n_sb + s];
+    float2 R[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const float g = __uint_as_float(
-          __builtin_amdgcn_raw_buffer_load_b32(grs, goff, 1024 * r, 0));
-      float c = fmaf(-A, g, bse);
-      c -= rintf(c);
-      const float sn = __builtin_amdgcn_sinf(c), cs = __builtin_amdgcn_cosf(c);
-      v[r] = cmul(U[r], make_float2(cs, -sn));
+      const float g = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+          grs, 4 * (s * kNfft + j), 1024 * r, 0));
+      U[r] = cmul(U[r], chirp(fmaf(-A, g, bse)));
+      float cr = fmaf(-dA, g, fdA);
+      cr -= rintf(cr);
+      float sn, cs;
+      sincospif(2.0f * cr, &sn, &cs);
+      R[r] = make_float2(cs, -sn);
     }
-    __syncthreads();  // previous trial's last LDS reads are done
-    fft4096<true>(v, lds, coarse, fine, jo);
-    float2 *out = d + (((long)b * n_tec + jt) * n_sb + s) * n_t + hs;
+    for (int jt = 0; jt < n_tec; ++jt) {
+      const int jo = opaque(j);
 #pragma unroll
-    for (int r = 8; r < 16; ++r)
-      out[j + 256 * (r - 8)] = make_float2(v[r].x * scale, v[r].y * scale);
+      for (int r = 0; r < 16; ++r) {
+        v[r] = U[r];
+        U[r] = cmul(U[r], R[r]);
+      }
+      __syncthreads();  // previous trial's last LDS reads are done
+      fft4096<true, true>(v, lds, tws, jo);
+      float2 *out = outb + jt * trial_stride;
+#pragma unroll
+      for (int r = 8; r < 16; ++r) out[256 * (r - 8)] = v[r];
+    }
+  } else {
+    for (int jt = 0; jt < n_tec; ++jt) {
+      const int jo = opaque(j);
+      const float bse = base[jt * n_sb + s] + e, A = afac[jt * n_sb + s];
+      const int goff = 4 * (s * kNfft + jo);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float g = __uint_as_float(
+            __builtin_amdgcn_raw_buffer_load_b32(grs, goff, 1024 * r, 0));
+        v[r] = cmul(U[r], chirp(fmaf(-A, g, bse)));
+      }
+      __syncthreads();  // previous trial's last LDS reads are done
+      fft4096<true, true>(v, lds, tws, jo);
+      float2 *out = outb + jt * trial_stride;
+#pragma unroll
+      for (int r = 8; r < 16; ++r) out[256 * (r - 8)] = v[r];
+    }
   }
 }
 
@@ -213,12 +299,13 @@ lp_status dd_launch(lp_ctx *ctx, DdPlan *p, int n_sb, const void *y,
   const long nb = (long)n_beams * n_sb * n_hop;
   if (nb > 0x7fffffffL)
     return set_error(LP_EINVAL, "lp_dedisperse: grid too large");
-  hipLaunchKernelGGL(dd_kernel, dim3((unsigned)nb), dim3(kDdThreads), 0, st,
+  auto kern = p->uniform ? dd_kernel<true> : dd_kernel<false>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kDdThreads), 0, st,
                      static_cast<const float2 *>(y), static_cast<float2 *>(tail),
                      update_tail ? 1 : 0, static_cast<float2 *>(d),
                      ctx->tw4096.as<const float2>(), p->base.as<const float>(),
-                     p->afac.as<const float>(), p->gq.as<const float>(), n_sb,
-                     p->n_tec, n_t, n_hop, nb);
+                     p->afac.as<const float>(), p->step.as<const float>(),
+                     p->gq.as<const float>(), n_sb, p->n_tec, n_t, n_hop, nb);
   LP_HIP(hipGetLastError());
   return LP_OK;
 }

@@ -144,6 +144,8 @@ struct DdPlan : PlanBase {
   DevBuf afac;    // f32 [J][S] kappa T / f_k in cycles
   DevBuf rfk;     // f32 [S] (subband rate / N_fft) / f_k
   DevBuf gq;      // f32 [S][N_fft] x / (1 + x), x = nu_q / f_k (signed bin q)
+  DevBuf step;    // f32 [2][S] frac(dA), dA = kappa dT / f_k (uniform grids)
+  bool uniform = false;  // n_tec >= 2 trials spaced by a constant dT
 };
 
 // Synthesis tables for one (band, prototype beta).

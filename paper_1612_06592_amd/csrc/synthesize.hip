@@ -11,9 +11,10 @@
 //
 // One 1024-thread workgroup per (series, block of F frames).  Frames are
 // transformed 16 at a time in a 139 KB LDS tile (radix 16, 16, 4 Stockham
-// passes, 64 threads per frame: pass 0 in the fetch layout, passes 1 and 2
-// by one wave per frame, with no workgroup barrier between them); thread
-// n then owns FIR column n and keeps
+// passes): wave w transforms frame w of each chunk on its own, so the
+// exchanges between passes stay inside the wave and a chunk needs two
+// workgroup barriers (transforms done; FIR done).  Thread n then owns FIR
+// column n and keeps
 // Z_{m-15..m}[n] and its 16 taps in registers, so each output sample costs
 // 16 complex-by-real FMAs and nothing is written to HBM except the
 // per-frame envelope maximum (+ arg), per-16-frame sums of (2 Re z)^2 and,
@@ -93,16 +94,14 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     SynCand *__restrict__ cand, float *__restrict__ psum, int n_sb, long n_t,
     long frame0, long warm, int F, long cand_nt, long cand_t0) {
   __shared__ float2 lds[16 * kSynFs];
-  // Twiddles per pass, so every read is a per-chunk base plus a constant
-  // offset (the lanes of one butterfly group read the same entry):
+  // Twiddles per pass, so every read is a per-lane base plus a constant
+  // offset:
   //   tw_p1[a][r] = exp(+2 pi i 4 a r / 1024)   (pass 1, a = j mod 16;
   //                 rows of 17 so the 16 rows a wave reads fall on distinct
   //                 banks)
   //   tw_p2[q][t] = exp(+2 pi i (q + 1) t / 1024) (pass 2, t < 256)
   __shared__ float2 tw_p1[16 * 17];
   __shared__ float2 tw_p2[3 * 256];
-  // Element offset si * n_t in d of bin j + 64 r (r < 8), or -1 if empty.
-  __shared__ int soff[8 * 64];
   __shared__ float red_s[16];
 
   const int series = blockIdx.y;
@@ -111,10 +110,6 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
   const int wave = tid >> 6, lane = tid & 63;
   const float2 *ds = d + (long)series * n_sb * n_t;
   float2 *hs = hist + (long)series * n_sb * kSynHist;
-
-  // FFT thread layout: frame f = tid % 16 (consecutive lanes read
-  // consecutive frames of one subband), butterfly j = tid / 16.
-  const int f = tid & 15, j = tid >> 4;
   const int n = tid;  // FIR column
 
   float2 win[16];
@@ -135,78 +130,66 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     }
     const float2 w = tw[4 * idx];
     *dst = make_float2(w.x, -w.y);
-    if (tid < 512) {
-      const int si = binmap[tid];  // bin (tid % 64) + 64 (tid / 64)
-      soff[tid] = si >= 0 ? si * (int)n_t : -1;
-    }
+  }
+  // Wave w transforms frame w of each 16-frame chunk; lane j is pass-0
+  // butterfly j, reading bins j + 64 r (r < NR).  Byte offset of each bin's
+  // row in the series, or the series size for empty bins (a raw buffer load
+  // past the end reads zero).
+  const unsigned ser_bytes = (unsigned)n_sb * (unsigned)n_t * 8u;
+  const __amdgpu_buffer_rsrc_t drs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float2 *>(ds), 0, (int)ser_bytes, kRawBufferWord3);
+  unsigned roff[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int si = binmap[lane + 64 * r];
+    roff[r] = si >= 0 ? (unsigned)si * (unsigned)n_t * 8u : ser_bytes;
   }
   __syncthreads();
 
   const int n_chunk = F / 16;
-  // Pass-0 inputs of a chunk: bins j + 64 r (r < NR; bins >= 64 NR are
-  // empty) of frame mc + f, from d or, before the block, from the history.
   float2 pre[NR];
   auto fetch = [&](long mc_) {
-    const int jo = opaque(j), fo = opaque(f);
-    if (mc_ >= 0) {
-      // Inside the block (every chunk but the first of workgroup 0):
-      // 32-bit byte offsets from the series base (n_sb * n_t * 8 < 2^32).
-      const int m = (int)mc_ + fo;
-      const char *db = reinterpret_cast<const char *>(ds);
+    const long m = mc_ + wave;
+    if (m >= 0) {
+      typedef unsigned u2 __attribute__((ext_vector_type(2)));
+      const unsigned mo = (unsigned)m * 8u;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        const int o = soff[64 * r + jo];
-        pre[r] = make_float2(0.f, 0.f);
-        if (o >= 0)
-          pre[r] = *reinterpret_cast<const float2 *>(db + (unsigned)(o + m) * 8u);
+        const u2 b = __builtin_amdgcn_raw_buffer_load_b64(drs, roff[r] + mo, 0, 0);
+        pre[r] = make_float2(__uint_as_float(b.x), __uint_as_float(b.y));
       }
     } else {
-      const long m = mc_ + fo;
+      // Before the stream block (warm-up chunk of workgroup 0): history.
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        int si = binmap[jo + 64 * r];
-        pre[r] = make_float2(0.f, 0.f);
-        if (si >= 0)
-          pre[r] = (m >= 0) ? ds[(long)si * n_t + m]
-                            : hs[si * kSynHist + (kSynHist + m)];
+        const int si = binmap[lane + 64 * r];
+        pre[r] = si >= 0 ? hs[si * kSynHist + (kSynHist + m)]
+                         : make_float2(0.f, 0.f);
       }
     }
   };
   fetch(m0 - 16);
   for (int c = -1; c < n_chunk; ++c) {
     const long mc = m0 + 16L * c;  // first frame of the chunk
-    // Per-chunk opaque copies of the thread indices keep address arithmetic
-    // inside the loop (hoisted, it would not fit in registers).
-    const int jo = opaque(j), no = opaque(n), fo = opaque(f);
-    const int lo = opaque(lane), wo = opaque(wave);
-    // ---- pass 0 (radix 16, Ns = 1).
+    const int no = opaque(n), lo = opaque(lane), wo = opaque(wave);
+    float2 *fr = lds + wo * kSynFs;
+    // ---- pass 0 (radix 16, Ns = 1) of frame wo: butterfly lo.  Every
+    // exchange of this frame stays inside the wave, whose LDS operations
+    // execute in issue order; the fences only keep the compiler from moving
+    // reads above the writes they depend on.
     float2 v[16];
 #pragma unroll
     for (int r = 0; r < NR; ++r) v[r] = pre[r];
 #pragma unroll
     for (int r = NR; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
     dft16<true>(v);
-    __syncthreads();  // previous chunk's FIR reads of lds are done
-    {
-      float2 *fr = lds + fo * kSynFs;
+    // pad16(16 j + r) = 17 j + r.
 #pragma unroll
-      for (int r = 0; r < 16; ++r) fr[pad16(16 * jo + r)] = v[r];
-    }
-    __syncthreads();
-    if (c == -1 && m0 == 0) {
-      // Every history read of this block happened above: store the new
-      // history, the last 16 frames of d.
-      for (int i = tid; i < n_sb * kSynHist; i += kSynThreads) {
-        int si = i / kSynHist, fi = i % kSynHist;
-        hs[i] = ds[(long)si * n_t + (n_t - kSynHist + fi)];
-      }
-    }
-    // ---- passes 1 and 2: wave w transforms frame w alone (lane = butterfly
-    // j), so the exchange between the passes stays inside the wave: its LDS
-    // operations execute in issue order, and the fence below only keeps the
-    // compiler from moving the pass-2 reads above the pass-1 writes.
+    for (int r = 0; r < 16; ++r) fr[17 * lo + r] = v[r];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     {
-      float2 *fr = lds + wo * kSynFs;
       // pad16(j + 64 r) = j + j / 16 + 68 r for j < 64.
       const int b1 = lo + (lo >> 4);
       // ---- pass 1 (radix 16, Ns = 16).
@@ -243,20 +226,9 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
         sl[816] = a3;
       }
     }
-    __syncthreads();
-    // Next chunk's inputs are in flight while this chunk is filtered.
-    if (c + 1 < n_chunk) fetch(mc + 16);
-    // ---- FIR, envelope, statistics for the 16 frames of this chunk.
-    if (c < 0) {
-#pragma unroll
-      for (int fi = 0; fi < 16; ++fi) win[fi] = lds[fi * kSynFs + pad16(no)];
-      continue;
-    }
-    // Taps (2 g) are reloaded per chunk (cache hits) so they do not occupy
-    // registers during the transform.
-    // A raw buffer view of the 16 x 1024 taps: tap t of column n is at the
-    // constant offset 4096 t plus 4 n, so the loads need no address
-    // arithmetic (offsets past the 64 KB view read as zero).
+    // Taps (2 g) of column n, in flight across the barrier.  A raw buffer
+    // view of the 16 x 1024 taps: tap t of column n is at the constant
+    // offset 4096 t plus 4 n.
     const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float *>(taps), 0, 16 * 1024 * 4, kRawBufferWord3);
     float g[16];
@@ -264,6 +236,24 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     for (int t = 0; t < 16; ++t)
       g[t] = __uint_as_float(
           __builtin_amdgcn_raw_buffer_load_b32(trs, 4 * no, 4096 * t, 0));
+    __syncthreads();  // every frame of the chunk is transformed
+    if (c == -1 && m0 == 0) {
+      // Every history read of this block happened above: store the new
+      // history, the last 16 frames of d.
+      for (int i = tid; i < n_sb * kSynHist; i += kSynThreads) {
+        int si = i / kSynHist, fi = i % kSynHist;
+        hs[i] = ds[(long)si * n_t + (n_t - kSynHist + fi)];
+      }
+    }
+    // Next chunk's inputs are in flight while this chunk is filtered.
+    if (c + 1 < n_chunk) fetch(mc + 16);
+    // ---- FIR, envelope, statistics for the 16 frames of this chunk.
+    if (c < 0) {
+#pragma unroll
+      for (int fi = 0; fi < 16; ++fi) win[fi] = lds[fi * kSynFs + pad16(no)];
+      __syncthreads();  // reads done before the next chunk's transforms
+      continue;
+    }
     float acc_s = 0.f;
     // Frames before `warm` (stream time) stay out of the statistics.
     const long fv = warm - (frame0 + mc);
@@ -367,8 +357,9 @@ lp_status syn_launch(lp_ctx *ctx, SynPlan *p, int n_sb, const void *d,
                      hipStream_t st) {
   lp_status rc;
   if ((rc = plan_wait(p, st))) return rc;
-  // The kernel addresses one series' subbands with 32-bit byte offsets.
-  if ((long)n_sb * n_t * 8 >= (1L << 32))
+  // The kernel addresses one series' subbands with 32-bit byte offsets
+  // (empty bins at one row past the end).
+  if ((long)(n_sb + 1) * n_t * 8 >= (1L << 32))
     return set_error(LP_EINVAL, "synthesis: %d subbands x %ld frames too large",
                      n_sb, n_t);
   // Frames per workgroup F: each workgroup transforms a 16-frame warm-up
