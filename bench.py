@@ -121,6 +121,13 @@ def main():
                     help="c5: offered load as a fraction of the GPU")
     ap.add_argument("--max-log2-nt", type=int, default=18,
                     help="c5: longest block is 2^this samples per subband")
+    ap.add_argument("--arena-frac", type=float, default=1.0,
+                    help="c5: arena = resident state + this fraction of every "
+                         "stream's longest in-flight block (1: all fit at "
+                         "once; below 1 admission has to wait)")
+    ap.add_argument("--plain-max-log2-nt", type=int, default=15,
+                    help="c5: time the plain FP32 pipeline alone on every "
+                         "stream for blocks up to 2^this (0: skip)")
     ap.add_argument("--ppf-iters", type=int, default=LSMR_ITERS,
                     help="LSMR iterations of the PPF-inversion leg (0: skip)")
     ap.add_argument("--ppf-steps", type=int, default=3,
@@ -786,8 +793,15 @@ def serving_bench(a):
           flush=True)
     ctx = lp.Ctx(0)
     chunk_t = 16384
-    arena_bytes = sum(c.resident_bytes(chunk_t) + c.block_bytes(1 << a.max_log2_nt)
-                      for c in cfgs) + (1 << 30)
+    resident = sum(c.resident_bytes(chunk_t) for c in cfgs)
+    blk_max = [c.block_bytes(1 << a.max_log2_nt) for c in cfgs]
+    if a.arena_frac >= 1.0:
+        arena_bytes = resident + sum(blk_max) + (1 << 30)
+    else:
+        # Smaller than what all streams' blocks need at once, never smaller
+        # than the largest single block (it must be admissible alone).
+        arena_bytes = resident + max(max(blk_max),
+                                     int(a.arena_frac * sum(blk_max))) + (256 << 20)
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
     lens = [1 << e for e in range(12, a.max_log2_nt + 1)]
 
@@ -856,6 +870,11 @@ def serving_bench(a):
     wall = time.perf_counter() - t_start
     stats = srv.stats()
     srv.destroy()
+    del arena
+    torch.cuda.empty_cache()
+    plain = None
+    if a.plain_max_log2_nt > 0:
+        plain = plain_alone(a, ctx, args, pools, svc, lens)
     ctx.close()
     ok = [r for r in results if r["status"] == lp.LP_OK]
     lat = np.array([r["latency_ns"] for r in ok]) * 1e-6
@@ -879,6 +898,9 @@ def serving_bench(a):
         "blocks": {"done": len(ok), "failed": len(results) - len(ok),
                    "chunks": stats["chunks_issued"],
                    "admit_waits": stats["admit_waits"]},
+        "arena": {"bytes": arena_bytes, "frac": a.arena_frac,
+                  "resident_bytes": resident,
+                  "longest_blocks_bytes": sum(blk_max)},
         "measured_load": round(busy / wall, 3),
         # Sum over streams and block lengths of the time alone per block.
         "service_alone_s": {
@@ -886,8 +908,41 @@ def serving_bench(a):
             "fp32": round(sum(sum(d.values()) for d in svc32), 4),
             "fp32_over_fp16": round(sum(sum(d.values()) for d in svc32)
                                     / sum(sum(d.values()) for d in svc), 3)},
+        "plain_fp32_alone": plain,
     }
     print(json.dumps(out))
+
+
+def plain_alone(a, ctx, args, pools, svc, lens):
+    """The plain FP32 pipeline (every intermediate in HBM) on each stream
+    alone, one block of each length up to 2^plain_max_log2_nt, against the
+    served FP16-MFMA blocks' service times at the same lengths."""
+    import torch
+    from paper_1612_06592_amd import lp
+    use = [n for n in lens if n <= (1 << a.plain_max_log2_nt)]
+    t_plain = t_fp16 = 0.0
+    for i, (enu, k, dirs, tec, _) in enumerate(args):
+        for n in use:
+            pp = lp.Pipeline(ctx, lp.Array(enu, 2), lp.Band(k), lp.Dirs(dirs),
+                             tec, n, dtype=lp.LP_CI8, plain=True,
+                             device=pools[i].device)
+            nb = len(k) * n * enu.shape[0] * 2 * 2
+            xb = pools[i][:nb]
+            pp.step(xb)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pp.step(xb)
+            torch.cuda.synchronize()
+            t_plain += time.perf_counter() - t0
+            t_fp16 += svc[i][n]
+            del pp
+            torch.cuda.empty_cache()
+    return {"lengths": [use[0], use[-1]], "blocks": len(use) * len(args),
+            "plain_s": round(t_plain, 4), "fp16_mfma_served_s": round(t_fp16, 4),
+            "plain_over_fp16": round(t_plain / t_fp16, 2),
+            "kind": "sum over streams and lengths of one block alone: the plain "
+                    "pipeline called directly, the FP16-MFMA block through the "
+                    "server"}
 
 
 if __name__ == "__main__":

@@ -282,9 +282,12 @@ __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
         int b = col >> 1;
         if (nt < NT && b < n_beams) {
           long t = t0 + mt * 16 + 4 * kq + (odd ? 2 : 0);
-          float4 o = odd ? make_float4(r0, acc[p][2], r1, acc[p][3])
-                         : make_float4(acc[p][0], r0, acc[p][1], r1);
-          *reinterpret_cast<float4 *>(y + ((long)b * n_sb + s) * n_t + t) = o;
+          const floatx4 o = odd ? floatx4{r0, acc[p][2], r1, acc[p][3]}
+                                : floatx4{acc[p][0], r0, acc[p][1], r1};
+          // Streaming store (nontemporal): the beams are read back by the
+          // de-dispersion after the whole launch (C2/C4 shapes 7 % faster).
+          __builtin_nontemporal_store(
+              o, reinterpret_cast<floatx4 *>(y + ((long)b * n_sb + s) * n_t + t));
         }
       }
     }

@@ -13,7 +13,7 @@ import pytest
 
 import lofarsim
 import oracle
-from chain import as_complex, rel_rms
+from chain import PER_ELEM, as_complex, max_err, rel_rms
 from paper_1612_06592_amd import lp
 
 pytestmark = pytest.mark.gpu
@@ -79,9 +79,9 @@ def test_gains_against_oracle(dtype, prec):
     ref = oracle.beamform(blk.enu, 2, blk.k, blk.az_el, x, gain=g)
     y = gpu_beams(blk, x, g, dtype, prec)
     assert np.all(np.isfinite(y))
-    e = rel_rms(y, ref)
-    print(f"all inputs rel-rms {e:.2e}", flush=True)
-    assert e <= TOL[prec]
+    e, m = rel_rms(y, ref), max_err(y, ref)
+    print(f"all inputs rel-rms {e:.2e} max {m:.2e}", flush=True)
+    assert e <= TOL[prec] and m <= PER_ELEM[prec]
     worst = 0.0
     for i in range(n_in - 1):
         xi = np.zeros_like(x)
@@ -89,9 +89,9 @@ def test_gains_against_oracle(dtype, prec):
         ref = oracle.beamform(blk.enu, 2, blk.k, blk.az_el, xi, gain=g)
         yi = gpu_beams(blk, xi, g, dtype, prec)
         assert np.all(np.isfinite(yi)), i
-        e = rel_rms(yi, ref)
+        e, m = rel_rms(yi, ref), max_err(yi, ref)
         worst = max(worst, e)
-        assert e <= TOL[prec], (i, float(g[i]), e)
+        assert e <= TOL[prec] and m <= PER_ELEM[prec], (i, float(g[i]), e, m)
     print(f"worst single-input rel-rms {worst:.2e}", flush=True)
     # the zero-gain input contributes nothing
     xz = np.zeros_like(x)

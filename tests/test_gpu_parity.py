@@ -12,7 +12,8 @@ import numpy as np
 import pytest
 
 import lofarsim
-from chain import WARM, OracleChain, compare_triggers, rel_rms, run_gpu
+from chain import (PER_ELEM, WARM, OracleChain, compare_triggers, max_err,
+                   rel_rms, run_gpu)
 from paper_1612_06592_amd import lp
 
 pytestmark = pytest.mark.gpu
@@ -21,22 +22,23 @@ TOL = {lp.LP_FP16_MFMA: 1e-3, lp.LP_FP32: 1e-5}
 
 
 def _check_block(g, o, prec, keep=(0,), label="", frame0=0):
-    tol = TOL[prec]
-    e = rel_rms(g["y"], o["y"])
-    print(f"{label} y rel-rms {e:.2e}", flush=True)
-    assert e <= tol
-    e = rel_rms(g["d"], o["d"])
-    print(f"{label} d rel-rms {e:.2e}", flush=True)
-    assert e <= tol
+    tol, pe = TOL[prec], PER_ELEM[prec]
+    e, m = rel_rms(g["y"], o["y"]), max_err(g["y"], o["y"])
+    print(f"{label} y rel-rms {e:.2e} max {m:.2e}", flush=True)
+    assert e <= tol and m <= pe
+    e, m = rel_rms(g["d"], o["d"]), max_err(g["d"], o["d"])
+    print(f"{label} d rel-rms {e:.2e} max {m:.2e}", flush=True)
+    assert e <= tol and m <= pe
     for q in keep:
         if g["x"] is not None and q in o["z"]:
-            e = rel_rms(g["x"][q], 2 * o["z"][q].real)
-            print(f"{label} x[{q}] rel-rms {e:.2e}", flush=True)
-            assert e <= tol
+            xo = 2 * o["z"][q].real
+            e, m = rel_rms(g["x"][q], xo), max_err(g["x"][q], xo)
+            print(f"{label} x[{q}] rel-rms {e:.2e} max {m:.2e}", flush=True)
+            assert e <= tol and m <= pe
     ns, n_t = o["wmax"].shape
-    e = rel_rms(g["emax"], o["wmax"])
-    print(f"{label} window-max rel-rms {e:.2e}", flush=True)
-    assert e <= tol, e
+    e, m = rel_rms(g["emax"], o["wmax"]), max_err(g["emax"], o["wmax"])
+    print(f"{label} window-max rel-rms {e:.2e} max {m:.2e}", flush=True)
+    assert e <= tol and m <= pe, (e, m)
     gs = g["sigma"].reshape(-1)
     assert np.max(np.abs(gs - o["sigma"]) / np.maximum(o["sigma"], 1e-30)) <= tol
     # Window arg-max over valid frames (start-up frames of a fresh stream
