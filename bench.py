@@ -134,6 +134,10 @@ def main():
                     help="timed PPF-inversion solves")
     ap.add_argument("--no-sim", action="store_true",
                     help="skip the station-simulator leg")
+    ap.add_argument("--trial-group", type=int, default=8,
+                    help="with several TEC trials: also time the chain with "
+                         "the de-dispersed subbands held for one beam's "
+                         "group of this many trials (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for "
                          "calibrating HBM byte counters)")
@@ -326,6 +330,10 @@ def main():
     if not a.no_sim:
         sim = station_sim_leg(a, ctx, cfg, blk, stream)
 
+    grouped = None
+    if cfg.n_tec > 1 and a.trial_group > 0:
+        grouped = trial_group_leg(a, ctx, p, cfg, blk, x, ms_per_step)
+
     plain = None
     if a.plain_steps > 0:
         del p
@@ -378,6 +386,7 @@ def main():
         "roofline": roofline,
         "whole_step": whole_step(cfg, ms_per_step),
         "error_vs_oracle": error,
+        "trial_groups": grouped,
         "plain_fp32_pipeline": plain,
         "ppf_inversion": ppf,
         "two_stage_beamforming": two,
@@ -386,6 +395,33 @@ def main():
     }
     ctx.close()
     print(json.dumps(out))
+
+
+def trial_group_leg(a, ctx, p, cfg, blk, x, ms_all):
+    """The chain with lp_dedisperse_synthesize: the de-dispersed subbands
+    held for one beam's group of a.trial_group trials instead of every
+    beam and trial; timed over 3 blocks after one."""
+    import torch
+    from paper_1612_06592_amd import lp
+    G = min(a.trial_group, cfg.n_tec)
+    pg = lp.Pipeline(ctx, p.array, p.band, p.dirs, p.tec, cfg.n_t,
+                     dtype=p.dtype, prec=p.prec, trial_group=G,
+                     device=x.device)
+    pg.step(x)
+    torch.cuda.synchronize()
+    n = 3
+    t0 = time.perf_counter()
+    for _ in range(n):
+        pg.step(x)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / n
+    d_all = cfg.n_beams * cfg.n_tec * cfg.n_sb * cfg.n_t * 8
+    d_grp = G * cfg.n_sb * cfg.n_t * 8
+    del pg
+    torch.cuda.empty_cache()
+    return {"trial_group": G, "d_bytes": d_grp, "d_bytes_all_trials": d_all,
+            "ms_per_step": round(ms, 3),
+            "vs_all_at_once": round(ms / ms_all, 3)}
 
 
 def ppf_bytes_per_iteration(n_sb: int, n_frames: int) -> float:

@@ -266,6 +266,31 @@ lp_status lp_synthesize(lp_ctx *ctx, const lp_band *band, const void *d,
                         void *hist, float *x_out, void *cand,
                         void *hip_stream);
 
+/* De-dispersion and synthesis of one block with the de-dispersed subbands
+ * held for one beam's group of trials only (Sec. 3: the STEC search repeats
+ * de-dispersion and inversion per trial value).  lp_dedisperse's d holds
+ * n_beams * n_tec * n_sb * n_t complex samples (28.7 GB for 7 beams x 32
+ * trials x 244 subbands x 65536); here the caller's work holds trial_group
+ * trials of one beam, and per beam and group of trials the two stages run
+ * back to back on hip_stream into the block's candidate array.  Every group
+ * transforms its hops forward again (more work for smaller groups).
+ *   y, tail : as lp_dedisperse (tail updated once, by each beam's last
+ *             group); hist, cand, frame0: as lp_synthesize for n_beams *
+ *             n_tec series (series = beam * n_tec + trial).
+ *   work    : device, >= lp_ddsyn_work_bytes(n_sb, n_t, min(trial_group,
+ *             n_tec)), 16-byte aligned; nothing is kept in it between calls.
+ * Outputs equal lp_dedisperse + lp_synthesize within the chirp rounding (a
+ * group's first trial takes its exact chirp; later trials step from it).
+ * Limits as both of those; trial_group >= 1, n_beams * n_tec <= 65535.   */
+size_t lp_ddsyn_work_bytes(int32_t n_sb, int64_t n_t, int32_t trial_group);
+lp_status lp_dedisperse_synthesize(lp_ctx *ctx, const lp_band *band,
+                                   const double *tec_tecu, int32_t n_tec,
+                                   const void *y, int32_t n_beams,
+                                   int64_t n_t, int64_t frame0, void *tail,
+                                   void *hist, void *cand,
+                                   int32_t trial_group, void *work,
+                                   size_t work_bytes, void *hip_stream);
+
 /* Trigger rules over one block's candidates (paper Sec. 2: the trigger that
  * reads out the transient buffers).  Every run of every series is kept and
  * merged, so the list equals the rules' full result whatever its length.

@@ -286,26 +286,31 @@ extern "C" lp_status lp_dedisperse(lp_ctx *ctx, const lp_band *band,
   PlanRef<DdPlan> p;
   if ((rc = get_dd_plan(ctx, band, tec_tecu, n_tec, st, p))) return rc;
   return dd_launch(ctx, p.get(), band->n_sb, y, n_beams, n_t, tail,
-                   !(flags & LP_DD_KEEP_TAIL), d, st);
+                   !(flags & LP_DD_KEEP_TAIL), d, 0, n_tec, st);
 }
 
 namespace lp {
 lp_status dd_launch(lp_ctx *ctx, DdPlan *p, int n_sb, const void *y,
                     int n_beams, long n_t, void *tail, bool update_tail,
-                    void *d, hipStream_t st) {
+                    void *d, int j0, int nj, hipStream_t st) {
   lp_status rc;
   if ((rc = plan_wait(p, st))) return rc;
   const int n_hop = (int)(n_t / kHop);
   const long nb = (long)n_beams * n_sb * n_hop;
   if (nb > 0x7fffffffL)
     return set_error(LP_EINVAL, "lp_dedisperse: grid too large");
-  auto kern = p->uniform ? dd_kernel<true> : dd_kernel<false>;
+  if (j0 < 0 || nj <= 0 || j0 + nj > p->n_tec)
+    return set_error(LP_EINVAL, "de-dispersion: trials %d..%d of %d", j0,
+                     j0 + nj - 1, p->n_tec);
+  auto kern = p->uniform && nj >= 2 ? dd_kernel<true> : dd_kernel<false>;
+  const size_t jo = (size_t)j0 * n_sb;
   hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kDdThreads), 0, st,
                      static_cast<const float2 *>(y), static_cast<float2 *>(tail),
                      update_tail ? 1 : 0, static_cast<float2 *>(d),
-                     ctx->tw4096.as<const float2>(), p->base.as<const float>(),
-                     p->afac.as<const float>(), p->step.as<const float>(),
-                     p->gq.as<const float>(), n_sb, p->n_tec, n_t, n_hop, nb);
+                     ctx->tw4096.as<const float2>(),
+                     p->base.as<const float>() + jo,
+                     p->afac.as<const float>() + jo, p->step.as<const float>(),
+                     p->gq.as<const float>(), n_sb, nj, n_t, n_hop, nb);
   LP_HIP(hipGetLastError());
   return LP_OK;
 }

@@ -263,13 +263,16 @@ lp_status trig_scratch_attach(int device);
 //   cand rows are cand_nt frames long and the block starts at cand_t0.
 lp_status bf_launch(BfPlan *p, const void *x, int dtype, long x_nt,
                     long x_t0, long n_t, int n_sb, void *y, hipStream_t st);
+//   dd_launch runs trials j0 .. j0 + nj - 1 of the plan's list (d holds nj
+//   trials per beam); syn_launch fills series series0 .. series0 + n_series
+//   - 1 of a candidate array laid out for n_series_total series.
 lp_status dd_launch(lp_ctx *ctx, DdPlan *p, int n_sb, const void *y,
                     int n_beams, long n_t, void *tail, bool update_tail,
-                    void *d, hipStream_t st);
+                    void *d, int j0, int nj, hipStream_t st);
 lp_status syn_launch(lp_ctx *ctx, SynPlan *p, int n_sb, const void *d,
                      int n_series, long n_t, long frame0, void *hist,
                      float *x_out, void *cand, long cand_nt, long cand_t0,
-                     hipStream_t st);
+                     int series0, int n_series_total, hipStream_t st);
 // Argument checks shared by lp_trigger and the serving loop.
 lp_status check_trigger_args(int n_beams, int n_tec, long n_t, long frame0,
                              float k_sigma, int cap);

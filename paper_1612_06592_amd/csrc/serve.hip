@@ -223,11 +223,11 @@ static lp_status issue_chunk(lp_server *s, Stream *st) {
                         A + st->y_off, st->hs)))
       return rc;
     if ((rc = dd_launch(s->ctx, st->dd, S, A + st->y_off, B, c,
-                        A + st->tail_off, true, A + st->d_off, st->hs)))
+                        A + st->tail_off, true, A + st->d_off, 0, J, st->hs)))
       return rc;
     if ((rc = syn_launch(s->ctx, st->syn, S, A + st->d_off, B * J, c,
                          b.frame0 + t0, A + st->hist_off, nullptr,
-                         ws + L.cand, b.n_t, t0, st->hs)))
+                         ws + L.cand, b.n_t, t0, 0, B * J, st->hs)))
       return rc;
     if (last) {
       if ((rc = trig_launch(ws + L.cand, B, J, b.n_t, b.frame0, st->k_sigma,

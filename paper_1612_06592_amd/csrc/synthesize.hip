@@ -347,14 +347,14 @@ extern "C" lp_status lp_synthesize(lp_ctx *ctx, const lp_band *band,
   PlanRef<SynPlan> p;
   if ((rc = get_syn_plan(ctx, band, st, p))) return rc;
   return syn_launch(ctx, p.get(), band->n_sb, d, n_series, n_t, frame0, hist,
-                    x_out, cand, n_t, 0, st);
+                    x_out, cand, n_t, 0, 0, n_series, st);
 }
 
 namespace lp {
 lp_status syn_launch(lp_ctx *ctx, SynPlan *p, int n_sb, const void *d,
                      int n_series, long n_t, long frame0, void *hist,
                      float *x_out, void *cand, long cand_nt, long cand_t0,
-                     hipStream_t st) {
+                     int series0, int n_series_total, hipStream_t st) {
   lp_status rc;
   if ((rc = plan_wait(p, st))) return rc;
   // The kernel addresses one series' subbands with 32-bit byte offsets
@@ -383,8 +383,9 @@ lp_status syn_launch(lp_ctx *ctx, SynPlan *p, int n_sb, const void *d,
   const long warm = kDelay + kTaps;
   const bool masked = frame0 < warm && (warm - frame0) % 16 != 0;
   char *cb = static_cast<char *>(cand);
-  SynCand *cd = reinterpret_cast<SynCand *>(cb);
-  float *ps = reinterpret_cast<float *>(cb + (size_t)n_series * cand_nt * 8);
+  SynCand *cd = reinterpret_cast<SynCand *>(cb) + (size_t)series0 * cand_nt;
+  float *ps = reinterpret_cast<float *>(cb + (size_t)n_series_total * cand_nt * 8) +
+              (size_t)series0 * (cand_nt / 16);
   // Kernel for the band's highest bin: pass-0 rows 4, 5, 6 or 8.
   decltype(&syn_kernel<false, 8>) kern;
   if (p->kmax < 256)

@@ -143,6 +143,13 @@ def lib():
                              vp, vp, vp, vp, vp]
     L.lp_trigger_noalloc.argtypes = [vp, vp, i32, i32, i64, i64, f32, vp,
                                      i32, vp, vp, vp, vp, vp]
+    L.lp_ddsyn_work_bytes.argtypes = [i32, i64, i32]
+    L.lp_ddsyn_work_bytes.restype = C.c_size_t
+    L.lp_dedisperse_synthesize.argtypes = [vp, C.POINTER(lp_band),
+                                           C.POINTER(C.c_double), i32, vp,
+                                           i32, i64, i64, vp, vp, vp, i32, vp,
+                                           C.c_size_t, vp]
+    L.lp_dedisperse_synthesize.restype = i32
     for name in ("lp_beamform", "lp_dedisperse", "lp_synthesize",
                  "lp_trigger", "lp_trigger_noalloc"):
         getattr(L, name).restype = i32
@@ -214,7 +221,8 @@ def exported_symbols():
             "lp_beam_bytes", "lp_dd_state_bytes", "lp_dd_bytes",
             "lp_syn_state_bytes", "lp_cand_bytes", "lp_trigger_work_bytes",
             "lp_beamform", "lp_dedisperse", "lp_synthesize", "lp_trigger",
-            "lp_trigger_noalloc",
+            "lp_trigger_noalloc", "lp_ddsyn_work_bytes",
+            "lp_dedisperse_synthesize",
             "lp_plain_work_bytes", "lp_dedisperse_plain",
             "lp_synthesize_plain", "lp_beamform_groups", "lp_beamform_stage2",
             "lp_ppf_analyze", "lp_ppf_adjoint",
@@ -348,6 +356,16 @@ def trigger(ctx: Ctx, cand, n_beams: int, n_tec: int, n_t: int, frame0: int,
                            _ptr(work), _stream(stream)))
 
 
+def dedisperse_synthesize(ctx: Ctx, band: Band, tec, y, n_beams: int,
+                          n_t: int, frame0: int, tail, hist, cand,
+                          trial_group: int, work, stream=None):
+    t = np.ascontiguousarray(np.atleast_1d(tec), dtype=np.float64)
+    check(lib().lp_dedisperse_synthesize(
+        ctx.h, C.byref(band.c), t.ctypes.data_as(C.POINTER(C.c_double)),
+        len(t), _ptr(y), n_beams, n_t, frame0, _ptr(tail), _ptr(hist),
+        _ptr(cand), trial_group, _ptr(work), work.numel(), _stream(stream)))
+
+
 def trigger_noalloc(ctx: Ctx, cand, n_beams: int, n_tec: int, n_t: int,
                     frame0: int, k_sigma: float, out, cap: int, n_out,
                     snr_out=None, best_tec=None, sigma_out=None, stream=None):
@@ -478,6 +496,8 @@ class Pipeline:
     trig_cap: int = 4096
     want_series: bool = False
     plain: bool = False          # plain FP32 comparator stages
+    trial_group: int = 0         # > 0: lp_dedisperse_synthesize, one beam's
+                                 # group of this many trials at a time
     device: str = "cuda:0"
     frame0: int = 0
     bufs: dict = field(default_factory=dict)
@@ -491,9 +511,12 @@ class Pipeline:
         def buf(n):
             return torch.empty(n, **u8)
 
+        grouped = 0 < self.trial_group and not self.plain
         self.bufs = dict(
             y=buf(nbytes("lp_beam_bytes", B, S, n_t)),
-            d=buf(nbytes("lp_dd_bytes", B, J, S, n_t)),
+            d=(buf(nbytes("lp_ddsyn_work_bytes", S, n_t,
+                          min(self.trial_group, J)))
+               if grouped else buf(nbytes("lp_dd_bytes", B, J, S, n_t))),
             tail=torch.zeros(nbytes("lp_dd_state_bytes", B, S), **u8),
             hist=torch.zeros(nbytes("lp_syn_state_bytes", B * J, S), **u8),
             cand=buf(nbytes("lp_cand_bytes", B * J, n_t)),
@@ -554,11 +577,23 @@ class Pipeline:
                 b["n_trig"], b["work"], b["snr"], b["best"], b["sigma"],
                 stream)
 
+    def dedisperse_synthesize(self, stream=None):
+        """Both stages, one beam's group of trial_group trials at a time
+        (bufs["d"] holds one group)."""
+        b = self.bufs
+        dedisperse_synthesize(self.ctx, self.band, self.tec, b["y"],
+                              self.n_beams, self.n_t, self.frame0, b["tail"],
+                              b["hist"], b["cand"], self.trial_group, b["d"],
+                              stream)
+
     def step(self, x, stream=None):
         """Whole chain on one block (asynchronous); advances the stream."""
         self.beamform(x, stream)
-        self.dedisperse(stream)
-        self.synthesize(stream)
+        if 0 < self.trial_group and not self.plain:
+            self.dedisperse_synthesize(stream)
+        else:
+            self.dedisperse(stream)
+            self.synthesize(stream)
         self.trigger(stream)
         self.frame0 += self.n_t
 
@@ -575,6 +610,8 @@ class Pipeline:
 
     def d_view(self):
         import torch
+        if 0 < self.trial_group and not self.plain:
+            raise ValueError("a trial-group pipeline holds one group of d")
         B, J, S = self.n_beams, self.n_tec, self.band.n_sb
         return self.bufs["d"].view(torch.float32).view(B, J, S, self.n_t, 2)
 

@@ -77,3 +77,16 @@ def test_one_hip_runtime_per_process():
                          text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.split() == ["1", "1"], out.stdout
+
+
+def test_dedisperse_synthesize_sizes_and_null_arguments():
+    L = lp.lib()
+    assert lp.nbytes("lp_ddsyn_work_bytes", 244, 65536, 8) == 8 * 244 * 65536 * 8
+    assert lp.nbytes("lp_ddsyn_work_bytes", 244, 65536, 0) == 0
+    band = lp.Band(range(52, 60))
+    tec = (C.c_double * 2)(0.0, 5.0)
+    rc = L.lp_dedisperse_synthesize(None, C.byref(band.c), tec, 2, None, 1,
+                                    2048, 0, None, None, None, 1, None, 0,
+                                    None)
+    assert rc == lp.LP_EINVAL
+    assert b"NULL" in L.lp_last_error()

@@ -426,3 +426,53 @@ def test_dedisperse_trial_grids(grid):
             assert e <= 1e-5, (j, e)
             assert m <= 1e-4, (j, m)
     ctx.close()
+
+
+@pytest.mark.parametrize("group", [1, 5])
+def test_trial_groups_equal_all_at_once(group):
+    """lp_dedisperse_synthesize (the de-dispersed subbands held for one
+    beam's group of trials) against lp_dedisperse + lp_synthesize over two
+    consecutive blocks of a 2-beam, 32-trial stream: window maxima, sigma,
+    peak SNR within the chirp-step rounding, identical trigger lists and best
+    trials; and both against the oracle."""
+    import torch
+    from chain import gpu_pipeline, to_device
+    tec = tuple(np.linspace(0, 30, 32).tolist())
+    cfg = lofarsim.get_config("c4", n_t=4096, k=tuple(range(52, 68)),
+                              n_pulses=1, snr=(30.0, 30.0), hex_rings=0)
+    blk = lofarsim.generate(cfg)
+    blk.az_el = np.concatenate([blk.az_el, blk.az_el + 0.002])
+    print("case trial groups", group, flush=True)
+    ctx, pa = gpu_pipeline(blk, lp.LP_FP16_MFMA, n_t=2048, want_series=False)
+    pg = lp.Pipeline(ctx, pa.array, pa.band, pa.dirs, pa.tec, 2048,
+                     dtype=pa.dtype, prec=pa.prec, trial_group=group)
+    oc = OracleChain(blk)
+    for i in range(2):
+        x = to_device(blk.x[:, 2048 * i:2048 * (i + 1)])
+        pa.step(x)
+        pg.step(x)
+        torch.cuda.synchronize()
+        ea, eg = pa.cand_view()[0].cpu().numpy(), pg.cand_view()[0].cpu().numpy()
+        e, m = rel_rms(eg, ea), max_err(eg, ea)
+        print(f"block {i}: grouped vs all-at-once window max rel-rms {e:.2e} "
+              f"max {m:.2e}", flush=True)
+        assert e <= 1e-5 and m <= 1e-4
+        sa, sg = pa.bufs["sigma"].cpu().numpy(), pg.bufs["sigma"].cpu().numpy()
+        assert np.max(np.abs(sg - sa) / sa) <= 1e-5
+        ta, tg = pa.triggers(), pg.triggers()
+        assert len(ta) == len(tg)
+        np.testing.assert_array_equal(ta["beam"], tg["beam"])
+        np.testing.assert_array_equal(ta["tec"], tg["tec"])
+        assert np.all(np.abs(ta["sample"] - tg["sample"]) <= 1)
+        assert np.array_equal(pa.bufs["best"].cpu().numpy(),
+                              pg.bufs["best"].cpu().numpy())
+        o = oc.process(blk.x[:, 2048 * i:2048 * (i + 1)])
+        e = rel_rms(eg, o["wmax"])
+        assert e <= 1e-3, e
+        miss, extra = compare_triggers(tg, o["trig"], o["sigma"])
+        print(f"block {i}: {len(tg)} triggers, oracle {len(o['trig'])}",
+              flush=True)
+        assert not miss and not extra, (miss, extra)
+    with pytest.raises(ValueError):
+        pg.d_view()
+    ctx.close()
