@@ -92,7 +92,8 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     const short *__restrict__ binmap, const float *__restrict__ taps,
     const float2 *__restrict__ tw, float *__restrict__ x_out,
     SynCand *__restrict__ cand, float *__restrict__ psum, int n_sb, long n_t,
-    long frame0, long warm, int F, long cand_nt, long cand_t0) {
+    long frame0, long warm, long per_wg, long total, long cand_nt,
+    long cand_t0) {
   __shared__ float2 lds[16 * kSynFs];
   // Twiddles per pass, so every read is a per-lane base plus a constant
   // offset:
@@ -103,13 +104,12 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
   __shared__ float2 tw_p1[16 * 17];
   __shared__ float2 tw_p2[3 * 256];
   __shared__ float red_s[16];
+  // Byte offset in the series of the row of bin j + 64 r (lane j), or the
+  // series size for an empty bin (a raw buffer load past the end reads 0).
+  __shared__ unsigned roff_s[8 * 64];
 
-  const int series = blockIdx.y;
-  const long m0 = (long)blockIdx.x * F;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const float2 *ds = d + (long)series * n_sb * n_t;
-  float2 *hs = hist + (long)series * n_sb * kSynHist;
   const int n = tid;  // FIR column
 
   float2 win[16];
@@ -132,194 +132,204 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     *dst = make_float2(w.x, -w.y);
   }
   // Wave w transforms frame w of each 16-frame chunk; lane j is pass-0
-  // butterfly j, reading bins j + 64 r (r < NR).  Byte offset of each bin's
-  // row in the series, or the series size for empty bins (a raw buffer load
-  // past the end reads zero).
+  // butterfly j, reading bins j + 64 r (r < NR) at the offsets in roff_s.
   const unsigned ser_bytes = (unsigned)n_sb * (unsigned)n_t * 8u;
-  const __amdgpu_buffer_rsrc_t drs = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<float2 *>(ds), 0, (int)ser_bytes, kRawBufferWord3);
-  unsigned roff[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const int si = binmap[lane + 64 * r];
-    roff[r] = si >= 0 ? (unsigned)si * (unsigned)n_t * 8u : ser_bytes;
+  if (tid < NR * 64) {
+    const int si = binmap[tid];
+    roff_s[tid] = si >= 0 ? (unsigned)si * (unsigned)n_t * 8u : ser_bytes;
   }
   __syncthreads();
 
-  const int n_chunk = F / 16;
-  float2 pre[NR];
-  auto fetch = [&](long mc_) {
-    const long m = mc_ + wave;
-    if (m >= 0) {
-      typedef unsigned u2 __attribute__((ext_vector_type(2)));
-      const unsigned mo = (unsigned)m * 8u;
+  // This workgroup's frames: [g, g_end) of the series-major frame index
+  // series * n_t + m, as segments of one series each (every segment starts
+  // with its own 16-frame warm-up chunk).
+  long g = (long)blockIdx.x * per_wg;
+  const long g_end = min(g + per_wg, total);
+  for (; g < g_end;) {
+    const int series = (int)(g / n_t);
+    const long m0 = g - (long)series * n_t;
+    const long seg = min(g_end - g, n_t - m0);
+    g += seg;
+    const float2 *ds = d + (long)series * n_sb * n_t;
+    float2 *hs = hist + (long)series * n_sb * kSynHist;
+    const __amdgpu_buffer_rsrc_t drs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float2 *>(ds), 0, (int)ser_bytes, kRawBufferWord3);
+    const int n_chunk = (int)(seg / 16);
+    float2 pre[NR];
+    auto fetch = [&](long mc_) {
+      const long m = mc_ + wave;
+      if (m >= 0) {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        const unsigned mo = (unsigned)m * 8u;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const u2 b = __builtin_amdgcn_raw_buffer_load_b64(drs, roff[r] + mo, 0, 0);
-        pre[r] = make_float2(__uint_as_float(b.x), __uint_as_float(b.y));
+        for (int r = 0; r < NR; ++r) {
+          const u2 b = __builtin_amdgcn_raw_buffer_load_b64(
+              drs, roff_s[64 * r + lane] + mo, 0, 0);
+          pre[r] = make_float2(__uint_as_float(b.x), __uint_as_float(b.y));
+        }
+      } else {
+        // Before the stream block (warm-up chunk of workgroup 0): history.
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const int si = binmap[lane + 64 * r];
+          pre[r] = si >= 0 ? hs[si * kSynHist + (kSynHist + m)]
+                           : make_float2(0.f, 0.f);
+        }
       }
-    } else {
-      // Before the stream block (warm-up chunk of workgroup 0): history.
+    };
+    fetch(m0 - 16);
+    for (int c = -1; c < n_chunk; ++c) {
+      const long mc = m0 + 16L * c;  // first frame of the chunk
+      const int no = opaque(n), lo = opaque(lane), wo = opaque(wave);
+      float2 *fr = lds + wo * kSynFs;
+      // ---- pass 0 (radix 16, Ns = 1) of frame wo: butterfly lo.  Every
+      // exchange of this frame stays inside the wave, whose LDS operations
+      // execute in issue order; the fences only keep the compiler from moving
+      // reads above the writes they depend on.
+      float2 v[16];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const int si = binmap[lane + 64 * r];
-        pre[r] = si >= 0 ? hs[si * kSynHist + (kSynHist + m)]
-                         : make_float2(0.f, 0.f);
-      }
-    }
-  };
-  fetch(m0 - 16);
-  for (int c = -1; c < n_chunk; ++c) {
-    const long mc = m0 + 16L * c;  // first frame of the chunk
-    const int no = opaque(n), lo = opaque(lane), wo = opaque(wave);
-    float2 *fr = lds + wo * kSynFs;
-    // ---- pass 0 (radix 16, Ns = 1) of frame wo: butterfly lo.  Every
-    // exchange of this frame stays inside the wave, whose LDS operations
-    // execute in issue order; the fences only keep the compiler from moving
-    // reads above the writes they depend on.
-    float2 v[16];
+      for (int r = 0; r < NR; ++r) v[r] = pre[r];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) v[r] = pre[r];
-#pragma unroll
-    for (int r = NR; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
-    dft16<true>(v);
-    // pad16(16 j + r) = 17 j + r.
-#pragma unroll
-    for (int r = 0; r < 16; ++r) fr[17 * lo + r] = v[r];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    {
-      // pad16(j + 64 r) = j + j / 16 + 68 r for j < 64.
-      const int b1 = lo + (lo >> 4);
-      // ---- pass 1 (radix 16, Ns = 16).
-#pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = fr[b1 + 68 * r];
-      {
-        const float2 *twr = tw_p1 + (lo & 15) * 17;  // 2 pi (j mod 16) r / 256
-#pragma unroll
-        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twr[r]);
-      }
+      for (int r = NR; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
       dft16<true>(v);
-      // pad16((j / 16) 256 + j mod 16 + 16 r) = (j / 16) 272 + j mod 16 + 17 r.
-      const int b2 = (lo >> 4) * 272 + (lo & 15);
+      // pad16(16 j + r) = 17 j + r.
 #pragma unroll
-      for (int r = 0; r < 16; ++r) fr[b2 + 17 * r] = v[r];
+      for (int r = 0; r < 16; ++r) fr[17 * lo + r] = v[r];
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // ---- pass 2 (radix 4, Ns = 256): butterflies j + 64 q, q < 4; each
-      // reads and writes the same four slots.
-      // Slot pad16(j + 64 q + 256 k) = j + j / 16 + 68 q + 272 k (j < 64).
+      {
+        // pad16(j + 64 r) = j + j / 16 + 68 r for j < 64.
+        const int b1 = lo + (lo >> 4);
+        // ---- pass 1 (radix 16, Ns = 16).
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int jt = lo + 64 * q;
-        float2 *sl = fr + b1 + 68 * q;
-        float2 a0 = sl[0], a1 = sl[272], a2 = sl[544], a3 = sl[816];
-        a1 = cmul(a1, tw_p2[jt]);
-        a2 = cmul(a2, tw_p2[256 + jt]);
-        a3 = cmul(a3, tw_p2[512 + jt]);
-        dft4<true>(a0, a1, a2, a3);
-        sl[0] = a0;
-        sl[272] = a1;
-        sl[544] = a2;
-        sl[816] = a3;
+        for (int r = 0; r < 16; ++r) v[r] = fr[b1 + 68 * r];
+        {
+          const float2 *twr = tw_p1 + (lo & 15) * 17;  // 2 pi (j mod 16) r / 256
+#pragma unroll
+          for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twr[r]);
+        }
+        dft16<true>(v);
+        // pad16((j / 16) 256 + j mod 16 + 16 r) = (j / 16) 272 + j mod 16 + 17 r.
+        const int b2 = (lo >> 4) * 272 + (lo & 15);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) fr[b2 + 17 * r] = v[r];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // ---- pass 2 (radix 4, Ns = 256): butterflies j + 64 q, q < 4; each
+        // reads and writes the same four slots.
+        // Slot pad16(j + 64 q + 256 k) = j + j / 16 + 68 q + 272 k (j < 64).
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int jt = lo + 64 * q;
+          float2 *sl = fr + b1 + 68 * q;
+          float2 a0 = sl[0], a1 = sl[272], a2 = sl[544], a3 = sl[816];
+          a1 = cmul(a1, tw_p2[jt]);
+          a2 = cmul(a2, tw_p2[256 + jt]);
+          a3 = cmul(a3, tw_p2[512 + jt]);
+          dft4<true>(a0, a1, a2, a3);
+          sl[0] = a0;
+          sl[272] = a1;
+          sl[544] = a2;
+          sl[816] = a3;
+        }
+      }
+      // Taps (2 g) of column n, in flight across the barrier.  A raw buffer
+      // view of the 16 x 1024 taps: tap t of column n is at the constant
+      // offset 4096 t plus 4 n.
+      const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float *>(taps), 0, 16 * 1024 * 4, kRawBufferWord3);
+      float g[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+        g[t] = __uint_as_float(
+            __builtin_amdgcn_raw_buffer_load_b32(trs, 4 * no, 4096 * t, 0));
+      __syncthreads();  // every frame of the chunk is transformed
+      if (c == -1 && m0 == 0) {
+        // Every history read of this block happened above: store the new
+        // history, the last 16 frames of d.
+        for (int i = tid; i < n_sb * kSynHist; i += kSynThreads) {
+          int si = i / kSynHist, fi = i % kSynHist;
+          hs[i] = ds[(long)si * n_t + (n_t - kSynHist + fi)];
+        }
+      }
+      // Next chunk's inputs are in flight while this chunk is filtered.
+      if (c + 1 < n_chunk) fetch(mc + 16);
+      // ---- FIR, envelope, statistics for the 16 frames of this chunk.
+      if (c < 0) {
+#pragma unroll
+        for (int fi = 0; fi < 16; ++fi) win[fi] = lds[fi * kSynFs + pad16(no)];
+        __syncthreads();  // reads done before the next chunk's transforms
+        continue;
+      }
+      float acc_s = 0.f;
+      // Frames before `warm` (stream time) stay out of the statistics.
+      const long fv = warm - (frame0 + mc);
+      const int first_valid = fv <= 0 ? 0 : (fv >= 16 ? 16 : (int)fv);
+      float *xo = x_out ? x_out + ((long)series * n_t + mc) * 1024 + no : nullptr;
+      // (zr, zi) = 2 z of frame fi: 2 Re z is the real series, |2 z|^2 the
+      // squared envelope; the slot is consumed, so it takes the latter, in
+      // its x word for columns with bit 4 clear and its y word otherwise (the
+      // 16-column groups then alternate between even and odd banks).
+      const int ecomp = (no >> 4) & 1;
+#pragma unroll
+      for (int fi = 0; fi < 16; ++fi) {
+        float2 *slot = lds + fi * kSynFs + pad16(no);
+        win[fi] = *slot;
+        float zr = 0.f, zi = 0.f;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          float2 w = win[(fi - t) & 15];
+          zr = fmaf(g[t], w.x, zr);
+          zi = fmaf(g[t], w.y, zi);
+        }
+        if (!MASKED || fi >= first_valid) acc_s = fmaf(zr, zr, acc_s);
+        if (xo) xo[(long)fi * 1024] = zr;
+        reinterpret_cast<float *>(slot)[ecomp] = zr * zr + zi * zi;
+      }
+      if (!MASKED && first_valid != 0) acc_s = 0.f;  // first_valid is 16
+      acc_s = wave_sum_dpp(acc_s);
+      if (lo == 63) red_s[wo] = acc_s;
+      __syncthreads();
+      // Wave w finds the envelope maximum of frame w and its lowest n: the
+      // maximum first, then per row n = 64 i + lane a ballot of the lanes
+      // holding it; the first row with a hit and its lowest lane give n.
+      // Squared envelopes are >= +0, so their bit patterns order as unsigned
+      // integers: the maximum is an exact selection.
+      {
+        // Lane l holds n = l + 64 i at slot pad16(n) = l + l / 16 + 68 i,
+        // envelope word (n / 16) mod 2 = (l / 16) mod 2.
+        const float *fl = reinterpret_cast<const float *>(
+                              lds + wo * kSynFs + lo + (lo >> 4)) +
+                          ((lo >> 4) & 1);
+        unsigned e2[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) e2[i] = __float_as_uint(fl[2 * 68 * i]);
+        unsigned bv = e2[0];
+#pragma unroll
+        for (int i = 1; i < 16; ++i) bv = max(bv, e2[i]);
+        bv = wave_umax_dpp(bv);
+        int bi = 0;
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+          const unsigned long long hit = __builtin_amdgcn_ballot_w64(e2[i] == bv);
+          if (hit) bi = 64 * i + __builtin_ctzll(hit);
+        }
+        if (lo == 0) {
+          SynCand o;
+          o.emax = sqrtf(__uint_as_float(bv));
+          o.arg = bi;
+          cand[(long)series * cand_nt + cand_t0 + mc + wo] = o;
+        }
+      }
+      if (tid == 64) {
+        float sum = 0.f;
+        for (int w = 0; w < 16; ++w) sum += red_s[w];
+        psum[(long)series * (cand_nt / 16) + (cand_t0 + mc) / 16] = sum;
       }
     }
-    // Taps (2 g) of column n, in flight across the barrier.  A raw buffer
-    // view of the 16 x 1024 taps: tap t of column n is at the constant
-    // offset 4096 t plus 4 n.
-    const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float *>(taps), 0, 16 * 1024 * 4, kRawBufferWord3);
-    float g[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t)
-      g[t] = __uint_as_float(
-          __builtin_amdgcn_raw_buffer_load_b32(trs, 4 * no, 4096 * t, 0));
-    __syncthreads();  // every frame of the chunk is transformed
-    if (c == -1 && m0 == 0) {
-      // Every history read of this block happened above: store the new
-      // history, the last 16 frames of d.
-      for (int i = tid; i < n_sb * kSynHist; i += kSynThreads) {
-        int si = i / kSynHist, fi = i % kSynHist;
-        hs[i] = ds[(long)si * n_t + (n_t - kSynHist + fi)];
-      }
-    }
-    // Next chunk's inputs are in flight while this chunk is filtered.
-    if (c + 1 < n_chunk) fetch(mc + 16);
-    // ---- FIR, envelope, statistics for the 16 frames of this chunk.
-    if (c < 0) {
-#pragma unroll
-      for (int fi = 0; fi < 16; ++fi) win[fi] = lds[fi * kSynFs + pad16(no)];
-      __syncthreads();  // reads done before the next chunk's transforms
-      continue;
-    }
-    float acc_s = 0.f;
-    // Frames before `warm` (stream time) stay out of the statistics.
-    const long fv = warm - (frame0 + mc);
-    const int first_valid = fv <= 0 ? 0 : (fv >= 16 ? 16 : (int)fv);
-    float *xo = x_out ? x_out + ((long)series * n_t + mc) * 1024 + no : nullptr;
-    // (zr, zi) = 2 z of frame fi: 2 Re z is the real series, |2 z|^2 the
-    // squared envelope; the slot is consumed, so it takes the latter, in
-    // its x word for columns with bit 4 clear and its y word otherwise (the
-    // 16-column groups then alternate between even and odd banks).
-    const int ecomp = (no >> 4) & 1;
-#pragma unroll
-    for (int fi = 0; fi < 16; ++fi) {
-      float2 *slot = lds + fi * kSynFs + pad16(no);
-      win[fi] = *slot;
-      float zr = 0.f, zi = 0.f;
-#pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        float2 w = win[(fi - t) & 15];
-        zr = fmaf(g[t], w.x, zr);
-        zi = fmaf(g[t], w.y, zi);
-      }
-      if (!MASKED || fi >= first_valid) acc_s = fmaf(zr, zr, acc_s);
-      if (xo) xo[(long)fi * 1024] = zr;
-      reinterpret_cast<float *>(slot)[ecomp] = zr * zr + zi * zi;
-    }
-    if (!MASKED && first_valid != 0) acc_s = 0.f;  // first_valid is 16
-    acc_s = wave_sum_dpp(acc_s);
-    if (lo == 63) red_s[wo] = acc_s;
-    __syncthreads();
-    // Wave w finds the envelope maximum of frame w and its lowest n: the
-    // maximum first, then per row n = 64 i + lane a ballot of the lanes
-    // holding it; the first row with a hit and its lowest lane give n.
-    // Squared envelopes are >= +0, so their bit patterns order as unsigned
-    // integers: the maximum is an exact selection.
-    {
-      // Lane l holds n = l + 64 i at slot pad16(n) = l + l / 16 + 68 i,
-      // envelope word (n / 16) mod 2 = (l / 16) mod 2.
-      const float *fl = reinterpret_cast<const float *>(
-                            lds + wo * kSynFs + lo + (lo >> 4)) +
-                        ((lo >> 4) & 1);
-      unsigned e2[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) e2[i] = __float_as_uint(fl[2 * 68 * i]);
-      unsigned bv = e2[0];
-#pragma unroll
-      for (int i = 1; i < 16; ++i) bv = max(bv, e2[i]);
-      bv = wave_umax_dpp(bv);
-      int bi = 0;
-#pragma unroll
-      for (int i = 15; i >= 0; --i) {
-        const unsigned long long hit = __builtin_amdgcn_ballot_w64(e2[i] == bv);
-        if (hit) bi = 64 * i + __builtin_ctzll(hit);
-      }
-      if (lo == 0) {
-        SynCand o;
-        o.emax = sqrtf(__uint_as_float(bv));
-        o.arg = bi;
-        cand[(long)series * cand_nt + cand_t0 + mc + wo] = o;
-      }
-    }
-    if (tid == 64) {
-      float sum = 0.f;
-      for (int w = 0; w < 16; ++w) sum += red_s[w];
-      psum[(long)series * (cand_nt / 16) + (cand_t0 + mc) / 16] = sum;
-    }
-  }
+  }  // segments
 }
 
 }  // namespace lp
@@ -362,24 +372,38 @@ lp_status syn_launch(lp_ctx *ctx, SynPlan *p, int n_sb, const void *d,
   if ((long)(n_sb + 1) * n_t * 8 >= (1L << 32))
     return set_error(LP_EINVAL, "synthesis: %d subbands x %ld frames too large",
                      n_sb, n_t);
-  // Frames per workgroup F: each workgroup transforms a 16-frame warm-up
-  // chunk besides its F frames, and one workgroup fills a CU, so F / (F +
-  // 16) times the occupancy of the last round of workgroups over the CUs is
-  // the efficiency; take the best F (the longest on ties).  n_t is a
-  // multiple of 2048, so every candidate divides it.
-  int F = 16;
+  // Frames per workgroup: each workgroup is one CU's tile for its life and
+  // walks a contiguous range of the series-major frame index, paying a
+  // 16-frame warm-up chunk for every series its range touches.  Candidates:
+  // the old lengths that divide n_t (ranges inside one series) and ranges
+  // of total / (k CUs) frames (k = 1, 2, 4, 8 rounds of workgroups); each
+  // scored by the frames filtered over the longest workgroup's work times
+  // the rounds (the longest range on ties).
+  const long total = (long)n_series * n_t;
+  long per_wg = 16;
   double best = -1.0;
-  for (int f : {2048, 1024, 512, 256, 128, 64, 32, 16}) {
-    const long nw = (long)n_series * (n_t / f);
+  auto consider = [&](long f) {
+    if (f <= 0) return;
+    const long nw = (total + f - 1) / f;
     const long rounds = (nw + ctx->n_cu - 1) / ctx->n_cu;
+    const long segs = (f % n_t == 0 || n_t % f == 0) ? (f + n_t - 1) / n_t
+                                                     : (f + n_t - 1) / n_t + 1;
     const double eff =
-        (double)f / (f + 16) * (double)nw / ((double)rounds * ctx->n_cu);
-    if (eff > best + 1e-12) {
+        (double)total / ((double)rounds * ctx->n_cu * (f + 16.0 * segs));
+    if (eff > best + 1e-12 || (eff > best - 1e-12 && f > per_wg)) {
       best = eff;
-      F = f;
+      per_wg = f;
     }
+  };
+  for (int f : {2048, 1024, 512, 256, 128, 64, 32, 16})
+    if (n_t % f == 0) consider(f);
+  for (int k : {1, 2, 4, 8}) {
+    const long slots = (long)k * ctx->n_cu;
+    consider(((total + slots - 1) / slots + 15) / 16 * 16);
   }
-  const long n_wg = n_t / F;
+  const long n_wg = (total + per_wg - 1) / per_wg;
+  if (n_wg > 0x7fffffffL)
+    return set_error(LP_EINVAL, "synthesis: grid too large");
   const long warm = kDelay + kTaps;
   const bool masked = frame0 < warm && (warm - frame0) % 16 != 0;
   char *cb = static_cast<char *>(cand);
@@ -396,12 +420,12 @@ lp_status syn_launch(lp_ctx *ctx, SynPlan *p, int n_sb, const void *d,
     kern = masked ? syn_kernel<true, 6> : syn_kernel<false, 6>;
   else
     kern = masked ? syn_kernel<true, 8> : syn_kernel<false, 8>;
-  hipLaunchKernelGGL(kern, dim3((unsigned)n_wg, n_series),
-                     dim3(kSynThreads), 0, st, static_cast<const float2 *>(d),
+  hipLaunchKernelGGL(kern, dim3((unsigned)n_wg), dim3(kSynThreads), 0, st,
+                     static_cast<const float2 *>(d),
                      static_cast<float2 *>(hist), p->binmap.as<const short>(),
                      p->taps2.as<const float>(), ctx->tw4096.as<const float2>(),
-                     x_out, cd, ps, n_sb, n_t, frame0, warm, F, cand_nt,
-                     cand_t0);
+                     x_out, cd, ps, n_sb, n_t, frame0, warm, per_wg, total,
+                     cand_nt, cand_t0);
   LP_HIP(hipGetLastError());
   return LP_OK;
 }
