@@ -586,6 +586,43 @@ class Pipeline:
                               b["hist"], b["cand"], self.trial_group, b["d"],
                               stream)
 
+    def step_graph(self, x):
+        """step() with beamform, de-dispersion and synthesis replayed from
+        a HIP graph captured on the first call with this input buffer.  The
+        three stages depend on frame0 only through the start-up rule, so the
+        graph is used once frame0 >= WARM_FRAMES (before that the block runs
+        as step()); the trigger, which reports samples from frame0, is issued
+        with the current frame0 after each replay.  No stage issues a memset
+        or host synchronisation, so the captured work is the eager work.
+        The graph holds the plan tables by address: it stays valid while the
+        context keeps this pipeline's plans (at most lp_ctx_plan_cache other
+        unused plans are created meanwhile)."""
+        import torch
+        if self.frame0 < WARM_FRAMES:
+            return self.step(x)
+        g = self.bufs.get("_graph")
+        if g is None or g[1] != x.data_ptr():
+            graph = torch.cuda.CUDAGraph()
+            cs = torch.cuda.Stream(device=self.device)
+            cs.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.graph(graph, stream=cs):
+                self._stages(x, None)
+            torch.cuda.current_stream().wait_stream(cs)
+            g = (graph, x.data_ptr())
+            self.bufs["_graph"] = g
+            # (capture records the work without running it)
+        g[0].replay()
+        self.trigger()
+        self.frame0 += self.n_t
+
+    def _stages(self, x, stream):
+        self.beamform(x, stream)
+        if 0 < self.trial_group and not self.plain:
+            self.dedisperse_synthesize(stream)
+        else:
+            self.dedisperse(stream)
+            self.synthesize(stream)
+
     def step(self, x, stream=None):
         """Whole chain on one block (asynchronous); advances the stream."""
         self.beamform(x, stream)
