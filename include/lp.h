@@ -148,8 +148,8 @@ void lp_ctx_destroy(lp_ctx *ctx);
  * LP_EINVAL if a plan is in use (an open serving stream).  dev = NULL goes
  * back to library-allocated tables.  When a new plan does not fit, unused
  * plans are evicted; if it still does not fit the call that needed it
- * returns LP_ENOMEM.  (A C2-sized band needs about 5 MB per chirp plan and
- * 0.2-12 MB per beam-weight plan.)                                         */
+ * returns LP_ENOMEM.  (A C2-sized band needs about 5 MB per chirp plan,
+ * 13 MB for a uniform grid of trials, and 0.2-12 MB per beam-weight plan.) */
 lp_status lp_ctx_bind_const(lp_ctx *ctx, void *dev, size_t bytes);
 /* Keep at most max_plans cached plans that no call or stream is using.    */
 lp_status lp_ctx_plan_cache(lp_ctx *ctx, int32_t max_plans);

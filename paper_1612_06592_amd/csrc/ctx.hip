@@ -199,6 +199,25 @@ __global__ void dd_ratio_kernel(const int *__restrict__ k, int n_sb, double f0,
   gq[i] = (float)(x / (1.0 + x));
 }
 
+// Ratio of consecutive trials' chirps on a uniform grid of spacing dT, per
+// subband and bin q (signed index q_s): exp(-2 pi i kappa dT / (f_k +
+// nu_q)) (the delay term does not depend on the trial).  Formed in FP64,
+// rounded once to FP32; one thread per entry.
+__global__ void dd_rstep_kernel(double dT, const int *__restrict__ k,
+                                int n_sb, double f0, double df, double kap,
+                                float2 *__restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)n_sb * kNfft) return;
+  const int s = (int)(i / kNfft), q = (int)(i % kNfft);
+  const int qs = q < kNfft / 2 ? q : q - kNfft;
+  const double f = f0 + (double)k[s] * df + (double)qs * (df / (double)kNfft);
+  double ph = kap * dT / f;
+  ph -= rint(ph);
+  double sn, cs;
+  sincospi(2.0 * ph, &sn, &cs);
+  out[i] = make_float2((float)cs, (float)-sn);
+}
+
 lp_status get_dd_plan(lp_ctx *ctx, const lp_band *band, const double *tec,
                       int n_tec, hipStream_t st, PlanRef<DdPlan> &out) {
   std::vector<uint8_t> key(1, kPlanDd);
@@ -226,30 +245,22 @@ lp_status get_dd_plan(lp_ctx *ctx, const lp_band *band, const double *tec,
       (rc = plan_alloc(ctx, p.get(), p->base, js * 4)) ||
       (rc = plan_alloc(ctx, p.get(), p->afac, js * 4)) ||
       (rc = plan_alloc(ctx, p.get(), p->rfk, (size_t)S * 4)) ||
-      (rc = plan_alloc(ctx, p.get(), p->gq, (size_t)S * kNfft * 4)) ||
-      (rc = plan_alloc(ctx, p.get(), p->step, (size_t)2 * S * 4)))
+      (rc = plan_alloc(ctx, p.get(), p->gq, (size_t)S * kNfft * 4)))
     return rc;
   // A uniform grid (at least two trials, T_t = T_0 + t dT) lets the kernel
-  // step the chirp from trial to trial: per subband the step's phase
-  // kappa dT / f_k, range-reduced in FP64.
-  std::vector<float> stp((size_t)2 * S, 0.0f);
+  // step the chirp from trial to trial by a per-bin factor.
+  double dT = 0.0;
   if (n_tec >= 2) {
-    const double dT = (tec[n_tec - 1] - tec[0]) / (n_tec - 1);
+    dT = (tec[n_tec - 1] - tec[0]) / (n_tec - 1);
     bool uni = true;
     for (int j = 0; j < n_tec; ++j)
       if (std::fabs(tec[j] - (tec[0] + j * dT)) >
           1e-9 * std::max(1.0, std::fabs(tec[n_tec - 1])))
         uni = false;
     p->uniform = uni;
-    const double kap = kappa_per_tecu(), df = band->fs_hz / kM;
-    for (int s = 0; s < S; ++s) {
-      const double fk = band->f0_hz + (double)band->k[s] * df;
-      const double dA = kap * dT / fk;
-      stp[s] = (float)(dA - std::rint(dA));
-      stp[(size_t)S + s] = (float)dA;
-    }
   }
-  if ((rc = plan_upload(p.get(), p->step, stp.data(), stp.size() * 4, st)))
+  if (p->uniform && (rc = plan_alloc(ctx, p.get(), p->rstep,
+                                    (size_t)S * kNfft * sizeof(float2))))
     return rc;
   const double *dtec = p->params.as<const double>();
   const int *dk = reinterpret_cast<const int *>(p->params.as<const char>() +
@@ -265,6 +276,13 @@ lp_status get_dd_plan(lp_ctx *ctx, const lp_band *band, const double *tec,
                      dim3(256), 0, st, dk, S, band->f0_hz, band->fs_hz / kM,
                      p->gq.as<float>());
   LP_HIP(hipGetLastError());
+  if (p->uniform) {
+    hipLaunchKernelGGL(dd_rstep_kernel, dim3((unsigned)((ng + 255) / 256)),
+                       dim3(256), 0, st, dT, dk, S, band->f0_hz,
+                       band->fs_hz / kM, kappa_per_tecu(),
+                       p->rstep.as<float2>());
+    LP_HIP(hipGetLastError());
+  }
   DdPlan *raw = p.get();
   if ((rc = plan_insert(ctx, std::move(p), st))) return rc;
   out.p = raw;

@@ -11,10 +11,14 @@
 // two exchanges through a padded 34 KB LDS tile.  Each thread's base
 // twiddle of a pass comes from two small LDS tables and its powers from a
 // product tree (tables of all powers were measured slower: this kernel is
-// close to bound by LDS instructions as well as VALU).  The forward spectrum stays in registers across all trials; on a uniform trial
-// grid the chirp of trial t + 1 is that of trial t times a fixed per-bin
-// factor, so each trial costs one complex product per bin instead of a
-// sine and a cosine.
+// close to bound by LDS instructions as well as VALU).  The forward
+// spectrum stays in registers across all trials.  A trial's chirp phase is
+// formed per bin from FP64-reduced constants and taken through the
+// hardware sine and cosine; on a uniform grid only the first trial's is,
+// and trial t + 1's chirp is trial t's times a per-bin factor read from a
+// table formed in FP64 (a table of every trial's factors, one complex load
+// per bin and trial instead of the phase, made the single-trial workloads
+// slower: C3 2.70 -> 2.79 ms).
 #include <cmath>
 
 #include "fft_dev.h"
@@ -142,17 +146,16 @@ __device__ __forceinline__ float2 chirp(float c) {
   return make_float2(__builtin_amdgcn_cosf(c), -__builtin_amdgcn_sinf(c));
 }
 
-// REC: the trials are uniformly spaced (step[0][s] = frac(dA), step[1][s] =
-// dA with dA = kappa dT / f_k), so trial t + 1's chirp is trial t's times
-// exp(-2 pi i (frac(dA) - dA g_q)); the per-bin factor is formed once per
-// hop with the accurate sincospi.
+// REC: the trials are uniformly spaced, so the first trial's chirp comes
+// from its phase and each next one is the previous one times
+// rstep[s][q] (float2 [S][N_fft]).
 template <bool REC>
 __global__ __launch_bounds__(kDdThreads)
 __attribute__((amdgpu_waves_per_eu(4, 8))) void dd_kernel(
     const float2 *__restrict__ y, float2 *__restrict__ tail, int update_tail,
     float2 *__restrict__ d, const float2 *__restrict__ tw,
     const float *__restrict__ base, const float *__restrict__ afac,
-    const float *__restrict__ step, const float *__restrict__ gq, int n_sb,
+    const float2 *__restrict__ rstep, const float *__restrict__ gq, int n_sb,
     int n_tec, long n_t, int n_hop, long n_blocks) {
   __shared__ float2 lds[kDdLds];
   __shared__ DdTw tws;
@@ -206,20 +209,16 @@ __attribute__((amdgpu_waves_per_eu(4, 8))) void dd_kernel(
   float2 *outb = d + ((long)b * n_tec * n_sb + s) * n_t + hs + j;
   const long trial_stride = (long)n_sb * n_t;
   if (REC) {
-    // U becomes trial 0's chirped spectrum; R the per-trial factor.
+    // U becomes the first trial's chirped spectrum; R the per-trial factor.
     const float bse = base[s] + e, A = afac[s];
-    const float fdA = step[s], dA = step[n_sb + s];
+    const float2 *rs = rstep + s * kNfft + j;
     float2 R[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const float g = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
           grs, 4 * (s * kNfft + j), 1024 * r, 0));
       U[r] = cmul(U[r], chirp(fmaf(-A, g, bse)));
-      float cr = fmaf(-dA, g, fdA);
-      cr -= rintf(cr);
-      float sn, cs;
-      sincospif(2.0f * cr, &sn, &cs);
-      R[r] = make_float2(cs, -sn);
+      R[r] = rs[256 * r];
     }
     for (int jt = 0; jt < n_tec; ++jt) {
       const int jo = opaque(j);
@@ -302,14 +301,15 @@ lp_status dd_launch(lp_ctx *ctx, DdPlan *p, int n_sb, const void *y,
   if (j0 < 0 || nj <= 0 || j0 + nj > p->n_tec)
     return set_error(LP_EINVAL, "de-dispersion: trials %d..%d of %d", j0,
                      j0 + nj - 1, p->n_tec);
-  auto kern = p->uniform && nj >= 2 ? dd_kernel<true> : dd_kernel<false>;
   const size_t jo = (size_t)j0 * n_sb;
+  auto kern = p->uniform && nj >= 2 ? dd_kernel<true> : dd_kernel<false>;
   hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(kDdThreads), 0, st,
                      static_cast<const float2 *>(y), static_cast<float2 *>(tail),
                      update_tail ? 1 : 0, static_cast<float2 *>(d),
                      ctx->tw4096.as<const float2>(),
                      p->base.as<const float>() + jo,
-                     p->afac.as<const float>() + jo, p->step.as<const float>(),
+                     p->afac.as<const float>() + jo,
+                     p->rstep.as<const float2>(),
                      p->gq.as<const float>(), n_sb, nj, n_t, n_hop, nb);
   LP_HIP(hipGetLastError());
   return LP_OK;

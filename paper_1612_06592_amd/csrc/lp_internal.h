@@ -144,7 +144,9 @@ struct DdPlan : PlanBase {
   DevBuf afac;    // f32 [J][S] kappa T / f_k in cycles
   DevBuf rfk;     // f32 [S] (subband rate / N_fft) / f_k
   DevBuf gq;      // f32 [S][N_fft] x / (1 + x), x = nu_q / f_k (signed bin q)
-  DevBuf step;    // f32 [2][S] frac(dA), dA = kappa dT / f_k (uniform grids)
+  // float2 [S][N_fft] factor from one trial's chirp to the next's on a
+  // uniform grid (present when `uniform`).
+  DevBuf rstep;
   bool uniform = false;  // n_tec >= 2 trials spaced by a constant dT
 };
 
