@@ -131,6 +131,12 @@ __device__ __forceinline__ int word_to_half2(unsigned w, half2v *out) {
   }
 }
 
+// Value of lane l ^ 1 (DPP quad_perm 1,0,3,2; a VALU move, no LDS).
+__device__ __forceinline__ float lane_swap1(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+}
+
 // LDS row stride (bytes) of the staged kernel's raw tile: KS*16 samples
 // plus 16 bytes.  For int8 rows the stride in 32-bit words is 4 KS + 4;
 // lanes (row r, quarter kq) then read words r (4 KS + 4) + 4 ks + kq.
@@ -162,7 +168,7 @@ __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
   typedef typename VecT<VB>::type V;
   constexpr int EPV = VB / (int)sizeof(IT);      // samples per vector
   extern __shared__ __attribute__((aligned(16))) unsigned char smb[];
-  const int RSB = bf_row_stride(KS, (int)sizeof(IT));
+  const int RSB = bf_row_stride(KSM, (int)sizeof(IT));
   _Float16 *xs_lds = reinterpret_cast<_Float16 *>(smb + T * RSB);
   const int s = blockIdx.y;
   const int tid = threadIdx.x;
@@ -186,13 +192,16 @@ __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
                         : z;
     }
   }
-  // Samples RK .. KS*16-1 of each row multiply zero weights; they are
-  // zeroed once (the tiles never write them), as are the scale factors.
-  const int padb = (KS * 16 - RK) * (int)sizeof(IT);
+  // Samples RK .. KSM*16-1 of each row multiply zero weights (the weight
+  // fragments of k-steps KS .. KSM-1 are zero too); they are zeroed once
+  // (the tiles never write them), as are the scale factors past KS*16.
+  // Every k-step then runs unconditionally.
+  const int padb = (KSM * 16 - RK) * (int)sizeof(IT);
   for (int i = tid; i < T * padb; i += kBfThreads)
     smb[(i / padb) * RSB + RK * (int)sizeof(IT) + (i % padb)] = 0;
   if (scaled)
-    for (int i = tid; i < KS * 16; i += kBfThreads) xs_lds[i] = xscale[i];
+    for (int i = tid; i < KSM * 16; i += kBfThreads)
+      xs_lds[i] = i < KS * 16 ? xscale[i] : (_Float16)0.0f;
 
   // LDS byte offset of each of this thread's load vectors within a tile
   // (the same for every tile; -1 past the tile).  row = v / vpr through
@@ -238,7 +247,10 @@ __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
     // before the barrier.
     if (tile + 1 < tiles_per_wg && t0 + T < n_t) fetch(t0 + T);
     __syncthreads();
-    for (int mi = 0; mi < mt_per_wave; ++mi) {
+    // The k-steps run without branches (the scaling choice is taken once
+    // per tile), so the accumulators stay in place across the MFMA chain.
+    auto mtile = [&](int mi, auto sc_c) {
+      constexpr bool SC = decltype(sc_c)::value;
       int mt = wm * mt_per_wave + mi;
       int row = mt * 16 + col16;
       const unsigned char *rp = smb + row * RSB;
@@ -247,50 +259,56 @@ __global__ __launch_bounds__(kBfThreads) void bf_mfma_kernel(
       for (int p = 0; p < NPW; ++p) acc[p] = floatx4{0, 0, 0, 0};
 #pragma unroll
       for (int ks = 0; ks < KSM; ++ks) {
-        if (ks < KS) {
-          // Samples ks*16 + 4*kq .. + 3 of the lane's row.
-          half2v h[2];
-          if constexpr (sizeof(IT) == 1) {
-            word_to_half2<IT>(
-                *reinterpret_cast<const unsigned *>(rp + ks * 16 + 4 * kq), h);
-          } else {
-            uint2 w2 = *reinterpret_cast<const uint2 *>(rp + ks * 32 + 8 * kq);
-            word_to_half2<IT>(w2.x, h);
-            word_to_half2<IT>(w2.y, h + 1);
-          }
-          half4 a = {h[0][0], h[0][1], h[1][0], h[1][1]};
-          if (scaled)
-            a = a * *reinterpret_cast<const half4 *>(xs_lds + ks * 16 + 4 * kq);
-#pragma unroll
-          for (int p = 0; p < NPW; ++p)
-            acc[p] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, wreg[p][ks],
-                                                           acc[p], 0, 0, 0);
+        // Samples ks*16 + 4*kq .. + 3 of the lane's row.
+        half2v h[2];
+        if constexpr (sizeof(IT) == 1) {
+          word_to_half2<IT>(
+              *reinterpret_cast<const unsigned *>(rp + ks * 16 + 4 * kq), h);
+        } else {
+          uint2 w2 = *reinterpret_cast<const uint2 *>(rp + ks * 32 + 8 * kq);
+          word_to_half2<IT>(w2.x, h);
+          word_to_half2<IT>(w2.y, h + 1);
         }
+        half4 a = {h[0][0], h[0][1], h[1][0], h[1][1]};
+        if constexpr (SC)
+          a = a * *reinterpret_cast<const half4 *>(xs_lds + ks * 16 + 4 * kq);
+#pragma unroll
+        for (int p = 0; p < NPW; ++p)
+          acc[p] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, wreg[p][ks],
+                                                         acc[p], 0, 0, 0);
       }
       // Lane holds D[4 kq + r][col16], r = 0..3.  Even columns are the real
-      // parts and odd columns the imaginary parts of beam col/2: swap half of
-      // the rows with the neighbour lane so each lane writes two complex.
+      // parts and odd columns the imaginary parts of beam col/2: each lane
+      // takes its neighbour's four values (DPP quad_perm 1,0,3,2: lane l
+      // reads lane l ^ 1), so the even lane writes rows 0, 1 and the odd
+      // lane rows 2, 3 as two complex each.  (Selecting by component
+      // between the lane's own and the neighbour's registers keeps every
+      // accumulator index constant.)
 #pragma unroll
       for (int p = 0; p < NPW; ++p) {
         int nt = wn + p * WN;
         int col = nt * 16 + col16;
         bool odd = col & 1;
-        float s0 = odd ? acc[p][0] : acc[p][2];
-        float s1 = odd ? acc[p][1] : acc[p][3];
-        float r0 = __shfl_xor(s0, 1);
-        float r1 = __shfl_xor(s1, 1);
+        const float a0 = acc[p][0], a1 = acc[p][1], a2 = acc[p][2],
+                    a3 = acc[p][3];
+        const float n0 = lane_swap1(a0), n1 = lane_swap1(a1),
+                    n2 = lane_swap1(a2), n3 = lane_swap1(a3);
         int b = col >> 1;
         if (nt < NT && b < n_beams) {
           long t = t0 + mt * 16 + 4 * kq + (odd ? 2 : 0);
-          const floatx4 o = odd ? floatx4{r0, acc[p][2], r1, acc[p][3]}
-                                : floatx4{acc[p][0], r0, acc[p][1], r1};
+          const floatx4 o = {odd ? n2 : a0, odd ? a2 : n0, odd ? n3 : a1,
+                             odd ? a3 : n1};
           // Streaming store (nontemporal): the beams are read back by the
           // de-dispersion after the whole launch (C2/C4 shapes 7 % faster).
           __builtin_nontemporal_store(
               o, reinterpret_cast<floatx4 *>(y + ((long)b * n_sb + s) * n_t + t));
         }
       }
-    }
+    };
+    if (scaled)
+      for (int mi = 0; mi < mt_per_wave; ++mi) mtile(mi, std::true_type());
+    else
+      for (int mi = 0; mi < mt_per_wave; ++mi) mtile(mi, std::false_type());
   }
 }
 
@@ -539,7 +557,11 @@ static lp_status launch_bf(const BfPlan *p, const void *x, long x_nt,
     // more workgroups in flight), four otherwise: measured on MI355X.
     const int tpw = tiles >= 8 ? (NT == 1 ? 2 : 4) : 1;
     dim3 grid((unsigned)((tiles + tpw - 1) / tpw), n_sb);
-    size_t shm = (size_t)T * bf_row_stride(KS, (int)sizeof(IT)) + KS * 32;
+    // k-steps per kernel instance (KSM >= KS; the extra ones multiply
+    // zeros): the LDS rows hold KSM*16 samples.
+    const int ksm = vb == 16 ? (KS <= 6 ? 6 : KS <= 8 ? 8 : KS <= 12 ? 12 : 16)
+                             : (KS <= 8 ? 8 : 16);
+    size_t shm = (size_t)T * bf_row_stride(ksm, (int)sizeof(IT)) + ksm * 32;
     auto args = [&](auto kern) {
       LP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
