@@ -38,10 +38,8 @@ __device__ __forceinline__ void dft16_hi(float2 *v) {
 #pragma unroll
   for (int n2 = 1; n2 < 4; ++n2) {
 #pragma unroll
-    for (int k1 = 1; k1 < 4; ++k1) {
-      float2 w = w16(n2 * k1);
-      v[n2 + 4 * k1] = INV ? cmulc(v[n2 + 4 * k1], w) : cmul(v[n2 + 4 * k1], w);
-    }
+    for (int k1 = 1; k1 < 4; ++k1)
+      v[n2 + 4 * k1] = tw16<INV>(v[n2 + 4 * k1], n2 * k1);
   }
   float2 o[8];
 #pragma unroll

@@ -66,20 +66,75 @@ __device__ __forceinline__ float2 w16(int m) {
   }
 }
 
-// 16-point DFT in place, natural order in and out (4 x 4 decomposition:
-// n = 4 n1 + n2, k = k1 + 4 k2).
+// v * W16^m (INV: times its conjugate).  W16^4 = -i is a swap and a sign
+// change (a general complex product by (0, -1) keeps two products by zero,
+// which IEEE arithmetic does not let the compiler drop).
 template <bool INV>
+__device__ __forceinline__ float2 tw16(float2 v, int m) {
+  if (m == 4)
+    return INV ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
+  const float2 w = w16(m);
+  return INV ? cmulc(v, w) : cmul(v, w);
+}
+
+// First radix-4 stage of a 16-point DFT on inputs x[n2], x[4 + n2],
+// x[8 + n2], x[12 + n2] of which only the first K are nonzero (K = 4: the
+// full 4-point DFT).  Known zeros are left out of the sums: IEEE arithmetic
+// keeps a + 0 (-0 + 0 is +0), so the compiler would not.
+template <bool INV, int K>
+__device__ __forceinline__ void dft4_first(float2 &a, float2 &b, float2 &c,
+                                           float2 &d) {
+  if constexpr (K >= 4) {
+    dft4<INV>(a, b, c, d);
+  } else if constexpr (K == 3) {  // d = 0
+    const float2 t0 = cadd(a, c), t1 = csub(a, c);
+    a = cadd(t0, b);
+    c = csub(t0, b);
+    // X1 = t1 -/+ i b, X3 = t1 +/- i b (forward / inverse)
+    const float2 ib = make_float2(-b.y, b.x);
+    d = INV ? csub(t1, ib) : cadd(t1, ib);
+    b = INV ? cadd(t1, ib) : csub(t1, ib);
+  } else if constexpr (K == 2) {  // c = d = 0
+    const float2 ib = make_float2(-b.y, b.x);
+    c = csub(a, b);
+    d = INV ? csub(a, ib) : cadd(a, ib);
+    const float2 x1 = INV ? cadd(a, ib) : csub(a, ib);
+    a = cadd(a, b);
+    b = x1;
+  } else {  // K == 1: every output is a
+    b = a;
+    c = a;
+    d = a;
+  }
+}
+
+// 16-point DFT in place, natural order in and out (4 x 4 decomposition:
+// n = 4 n1 + n2, k = k1 + 4 k2).  NZ: only inputs 0 .. NZ-1 can be nonzero
+// (the others are not read).
+template <bool INV, int NZ = 16>
 __device__ __forceinline__ void dft16(float2 *v) {
 #pragma unroll
-  for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+  for (int n2 = 0; n2 < 4; ++n2) {
+    // nonzero inputs among n2, n2 + 4, n2 + 8, n2 + 12 (a constant once
+    // the loop is unrolled)
+    const int k = NZ <= n2 ? 0 : (NZ - n2 + 3) / 4;
+    if (k >= 4)
+      dft4_first<INV, 4>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+    else if (k == 3)
+      dft4_first<INV, 3>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+    else if (k == 2)
+      dft4_first<INV, 2>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+    else if (k == 1)
+      dft4_first<INV, 1>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+    else
+      v[n2] = v[4 + n2] = v[8 + n2] = v[12 + n2] = make_float2(0.f, 0.f);
+  }
   // v[n2 + 4 k1] now holds A[n2][k1]; apply W16^(n2 k1).
 #pragma unroll
   for (int n2 = 1; n2 < 4; ++n2) {
 #pragma unroll
-    for (int k1 = 1; k1 < 4; ++k1) {
-      float2 w = w16(n2 * k1);
-      v[n2 + 4 * k1] = INV ? cmulc(v[n2 + 4 * k1], w) : cmul(v[n2 + 4 * k1], w);
-    }
+    for (int k1 = 1; k1 < 4; ++k1)
+      v[n2 + 4 * k1] = tw16<INV>(v[n2 + 4 * k1], n2 * k1);
   }
 #pragma unroll
   for (int k1 = 0; k1 < 4; ++k1)

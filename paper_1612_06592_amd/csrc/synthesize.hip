@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
       for (int r = 0; r < NR; ++r) v[r] = pre[r];
 #pragma unroll
       for (int r = NR; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
-      dft16<true>(v);
+      dft16<true, NR>(v);
       // pad16(16 j + r) = 17 j + r.
 #pragma unroll
       for (int r = 0; r < 16; ++r) fr[17 * lo + r] = v[r];
