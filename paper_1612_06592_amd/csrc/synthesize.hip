@@ -95,14 +95,13 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
     long frame0, long warm, long per_wg, long total, long cand_nt,
     long cand_t0) {
   __shared__ float2 lds[16 * kSynFs];
-  // Twiddles per pass, so every read is a per-lane base plus a constant
-  // offset:
-  //   tw_p1[a][r] = exp(+2 pi i 4 a r / 1024)   (pass 1, a = j mod 16;
-  //                 rows of 17 so the 16 rows a wave reads fall on distinct
-  //                 banks)
-  //   tw_p2[q][t] = exp(+2 pi i (q + 1) t / 1024) (pass 2, t < 256)
-  __shared__ float2 tw_p1[16 * 17];
-  __shared__ float2 tw_p2[3 * 256];
+  // Base twiddles of the two twiddled passes; each lane forms the powers it
+  // needs by products (reading every power from LDS tables was 4 % slower:
+  // the transform is bound by the latency of its LDS accesses):
+  //   tw_p1[a] = exp(+2 pi i 4 a / 1024)   (pass 1, a = j mod 16)
+  //   tw_p2[t] = exp(+2 pi i t / 1024)     (pass 2, t < 256)
+  __shared__ float2 tw_p1[16];
+  __shared__ float2 tw_p2[256];
   __shared__ float red_s[16];
   // Byte offset in the series of the row of bin j + 64 r (lane j), or the
   // series size for an empty bin (a raw buffer load past the end reads 0).
@@ -115,21 +114,11 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
   float2 win[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) win[t] = make_float2(0.f, 0.f);
-  {
-    // From the table exp(-2 pi i n / 4096), conjugated; every angle index
-    // here is below 1024.
-    int idx;
-    float2 *dst;
-    if (tid < 256) {
-      idx = 4 * (tid >> 4) * (tid & 15);
-      dst = tw_p1 + (tid >> 4) * 17 + (tid & 15);
-    } else {
-      const int e = tid - 256;
-      idx = (e / 256 + 1) * (e % 256);
-      dst = tw_p2 + e;
-    }
-    const float2 w = tw[4 * idx];
-    *dst = make_float2(w.x, -w.y);
+  if (tid < 256 + 16) {
+    // From the table exp(-2 pi i n / 4096), conjugated.
+    const int t = tid < 256 ? tid : 4 * (tid - 256);
+    const float2 w = tw[4 * t];
+    (tid < 256 ? tw_p2[tid] : tw_p1[tid - 256]) = make_float2(w.x, -w.y);
   }
   // Wave w transforms frame w of each 16-frame chunk; lane j is pass-0
   // butterfly j, reading bins j + 64 r (r < NR) at the offsets in roff_s.
@@ -205,9 +194,26 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = fr[b1 + 68 * r];
         {
-          const float2 *twr = tw_p1 + (lo & 15) * 17;  // 2 pi (j mod 16) r / 256
-#pragma unroll
-          for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twr[r]);
+          // v[r] *= w^r, w = exp(2 pi i (j mod 16) / 256): a product tree
+          // of depth 4, each power used as soon as it exists.
+          const float2 w1 = tw_p1[lo & 15];
+          const float2 w2 = cmul(w1, w1), w4 = cmul(w2, w2), w8 = cmul(w4, w4);
+          const float2 w3 = cmul(w2, w1), w7 = cmul(w4, w3);
+          v[1] = cmul(v[1], w1);
+          v[2] = cmul(v[2], w2);
+          v[3] = cmul(v[3], w3);
+          v[4] = cmul(v[4], w4);
+          v[5] = cmul(v[5], cmul(w4, w1));
+          v[6] = cmul(v[6], cmul(w4, w2));
+          v[7] = cmul(v[7], w7);
+          v[8] = cmul(v[8], w8);
+          v[9] = cmul(v[9], cmul(w8, w1));
+          v[10] = cmul(v[10], cmul(w8, w2));
+          v[11] = cmul(v[11], cmul(w8, w3));
+          v[12] = cmul(v[12], cmul(w8, w4));
+          v[13] = cmul(v[13], cmul(w8, cmul(w4, w1)));
+          v[14] = cmul(v[14], cmul(w8, cmul(w4, w2)));
+          v[15] = cmul(v[15], cmul(w8, w7));
         }
         dft16<true>(v);
         // pad16((j / 16) 256 + j mod 16 + 16 r) = (j / 16) 272 + j mod 16 + 17 r.
@@ -225,9 +231,10 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
           const int jt = lo + 64 * q;
           float2 *sl = fr + b1 + 68 * q;
           float2 a0 = sl[0], a1 = sl[272], a2 = sl[544], a3 = sl[816];
-          a1 = cmul(a1, tw_p2[jt]);
-          a2 = cmul(a2, tw_p2[256 + jt]);
-          a3 = cmul(a3, tw_p2[512 + jt]);
+          const float2 u1 = tw_p2[jt], u2 = cmul(u1, u1), u3 = cmul(u2, u1);
+          a1 = cmul(a1, u1);
+          a2 = cmul(a2, u2);
+          a3 = cmul(a3, u3);
           dft4<true>(a0, a1, a2, a3);
           sl[0] = a0;
           sl[272] = a1;
