@@ -12,7 +12,8 @@
 // One 1024-thread workgroup per (series, block of F frames).  Frames are
 // transformed 16 at a time in a 139 KB LDS tile (radix 16, 16, 4 Stockham
 // passes): wave w transforms frame w of each chunk on its own, so the
-// exchanges between passes stay inside the wave and a chunk needs two
+// exchanges between passes stay inside the wave (through LDS after pass 0,
+// by lane swaps across rows of 16 after pass 1) and a chunk needs two
 // workgroup barriers (transforms done; FIR done).  Thread n then owns FIR
 // column n and keeps
 // Z_{m-15..m}[n] and its 16 taps in registers, so each output sample costs
@@ -79,6 +80,30 @@ __device__ __forceinline__ unsigned wave_umax_dpp(unsigned v) {
   v = max(v, (unsigned)dpp_i<kDppBcast15, 0xA>((int)v, (int)v));
   v = max(v, (unsigned)dpp_i<kDppBcast31, 0xC>((int)v, (int)v));
   return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Row swaps across the wavefront (gfx950 v_permlane32/16_swap): with rows
+// of 16 lanes, swap_rows32 exchanges rows 2, 3 of a with rows 0, 1 of b;
+// swap_rows16 exchanges rows 1, 3 of a with rows 0, 2 of b.
+__device__ __forceinline__ void swap_rows32(float2 &a, float2 &b) {
+  const auto x = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.x),
+                                                  __float_as_uint(b.x), false,
+                                                  false);
+  const auto y = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.y),
+                                                  __float_as_uint(b.y), false,
+                                                  false);
+  a = make_float2(__uint_as_float(x[0]), __uint_as_float(y[0]));
+  b = make_float2(__uint_as_float(x[1]), __uint_as_float(y[1]));
+}
+__device__ __forceinline__ void swap_rows16(float2 &a, float2 &b) {
+  const auto x = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.x),
+                                                  __float_as_uint(b.x), false,
+                                                  false);
+  const auto y = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.y),
+                                                  __float_as_uint(b.y), false,
+                                                  false);
+  a = make_float2(__uint_as_float(x[0]), __uint_as_float(y[0]));
+  b = make_float2(__uint_as_float(x[1]), __uint_as_float(y[1]));
 }
 
 // MASKED: some chunk straddles the end of the warm-up (`warm` - frame0 not
@@ -216,21 +241,29 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
           v[15] = cmul(v[15], cmul(w8, w7));
         }
         dft16<true>(v);
-        // pad16((j / 16) 256 + j mod 16 + 16 r) = (j / 16) 272 + j mod 16 + 17 r.
-        const int b2 = (lo >> 4) * 272 + (lo & 15);
+        // Lane j now holds pass-1 output (j / 16) 256 + j mod 16 + 16 r in
+        // v[r].  The radix-4 butterfly jt = j + 64 q of pass 2 reads
+        // elements jt + 256 m (m < 4), held in v[4 q + j / 16] of lanes
+        // j mod 16 + 16 m: transposing, in each group of four registers,
+        // the lane's row of 16 (j / 16) against the register's low two bits
+        // (two swap steps across rows, no LDS) leaves element
+        // j + 64 q + 256 m in v[4 q + m].
 #pragma unroll
-        for (int r = 0; r < 16; ++r) fr[b2 + 17 * r] = v[r];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // ---- pass 2 (radix 4, Ns = 256): butterflies j + 64 q, q < 4; each
-        // reads and writes the same four slots.
-        // Slot pad16(j + 64 q + 256 k) = j + j / 16 + 68 q + 272 k (j < 64).
+        for (int q = 0; q < 4; ++q) {
+          swap_rows32(v[4 * q], v[4 * q + 2]);
+          swap_rows32(v[4 * q + 1], v[4 * q + 3]);
+          swap_rows16(v[4 * q], v[4 * q + 1]);
+          swap_rows16(v[4 * q + 2], v[4 * q + 3]);
+        }
+        // ---- pass 2 (radix 4, Ns = 256): butterflies j + 64 q, q < 4,
+        // written to their output slots
+        // pad16(j + 64 q + 256 k) = j + j / 16 + 68 q + 272 k (j < 64).
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int jt = lo + 64 * q;
           float2 *sl = fr + b1 + 68 * q;
-          float2 a0 = sl[0], a1 = sl[272], a2 = sl[544], a3 = sl[816];
+          float2 a0 = v[4 * q], a1 = v[4 * q + 1], a2 = v[4 * q + 2],
+                 a3 = v[4 * q + 3];
           const float2 u1 = tw_p2[jt], u2 = cmul(u1, u1), u3 = cmul(u2, u1);
           a1 = cmul(a1, u1);
           a2 = cmul(a2, u2);
