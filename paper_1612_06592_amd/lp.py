@@ -243,10 +243,33 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+_raw_stream = None
+
+
 def _stream(stream):
-    import torch
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return C.c_void_p(s.cuda_stream)
+    """HIP stream handle: `stream`'s, else the current stream of the current
+    device (read through torch's raw-stream query, which skips building a
+    Stream object: ~0.5 instead of ~3 us per call)."""
+    global _raw_stream
+    if stream is not None:
+        return C.c_void_p(stream.cuda_stream)
+    if _raw_stream is None:
+        import torch
+        torch.cuda.init()
+        q = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        _raw_stream = ((lambda: q(torch._C._cuda_getDevice())) if q else
+                       (lambda: torch.cuda.current_stream().cuda_stream))
+    return C.c_void_p(_raw_stream())
+
+
+def _tec(tec):
+    """(pointer, count) of the TEC trials: a ctypes double array as it is,
+    anything else through a contiguous float64 copy (kept alive by the
+    returned pointer object)."""
+    if isinstance(tec, C.Array):
+        return tec, len(tec)
+    t = np.ascontiguousarray(np.atleast_1d(tec), dtype=np.float64)
+    return t.ctypes.data_as(C.POINTER(C.c_double)), len(t)
 
 
 # ----------------------------------------------------------- descriptors
@@ -333,11 +356,10 @@ def beamform(ctx: Ctx, array: Array, band: Band, dirs: Dirs, x, n_t: int,
 
 def dedisperse(ctx: Ctx, band: Band, tec, y, n_beams: int, n_t: int, tail, d,
                flags: int = 0, stream=None):
-    t = np.ascontiguousarray(np.atleast_1d(tec), dtype=np.float64)
-    check(lib().lp_dedisperse(ctx.h, C.byref(band.c),
-                              t.ctypes.data_as(C.POINTER(C.c_double)), len(t),
-                              _ptr(y), n_beams, n_t, _ptr(tail), flags,
-                              _ptr(d), _stream(stream)))
+    tp, nt = _tec(tec)
+    check(lib().lp_dedisperse(ctx.h, C.byref(band.c), tp, nt, _ptr(y),
+                              n_beams, n_t, _ptr(tail), flags, _ptr(d),
+                              _stream(stream)))
 
 
 def synthesize(ctx: Ctx, band: Band, d, n_series: int, n_t: int, frame0: int,
@@ -359,10 +381,10 @@ def trigger(ctx: Ctx, cand, n_beams: int, n_tec: int, n_t: int, frame0: int,
 def dedisperse_synthesize(ctx: Ctx, band: Band, tec, y, n_beams: int,
                           n_t: int, frame0: int, tail, hist, cand,
                           trial_group: int, work, stream=None):
-    t = np.ascontiguousarray(np.atleast_1d(tec), dtype=np.float64)
+    tp, nt = _tec(tec)
     check(lib().lp_dedisperse_synthesize(
-        ctx.h, C.byref(band.c), t.ctypes.data_as(C.POINTER(C.c_double)),
-        len(t), _ptr(y), n_beams, n_t, frame0, _ptr(tail), _ptr(hist),
+        ctx.h, C.byref(band.c), tp, nt, _ptr(y), n_beams, n_t, frame0,
+        _ptr(tail), _ptr(hist),
         _ptr(cand), trial_group, _ptr(work), work.numel(), _stream(stream)))
 
 
@@ -381,11 +403,10 @@ TRIGGER_SCRATCH_BYTES = 128 << 20   # LP_TRIGGER_SCRATCH_BYTES
 
 def dedisperse_plain(ctx: Ctx, band: Band, tec, y, n_beams: int, n_t: int,
                      tail, d, work, flags: int = 0, stream=None):
-    t = np.ascontiguousarray(np.atleast_1d(tec), dtype=np.float64)
-    check(lib().lp_dedisperse_plain(ctx.h, C.byref(band.c),
-                                    t.ctypes.data_as(C.POINTER(C.c_double)),
-                                    len(t), _ptr(y), n_beams, n_t, _ptr(tail),
-                                    flags, _ptr(d), _ptr(work), work.numel(),
+    tp, nt = _tec(tec)
+    check(lib().lp_dedisperse_plain(ctx.h, C.byref(band.c), tp, nt, _ptr(y),
+                                    n_beams, n_t, _ptr(tail), flags, _ptr(d),
+                                    _ptr(work), work.numel(),
                                     _stream(stream)))
 
 
@@ -544,17 +565,27 @@ class Pipeline:
     def n_tec(self):
         return len(self.tec)
 
+    def _tec_arg(self):
+        """The trials as a ctypes double array, rebuilt whenever their values
+        change (a byte compare, cheaper than converting on every call)."""
+        key = np.ascontiguousarray(self.tec, dtype=np.float64).tobytes()
+        c = self.__dict__.get("_tec_c")
+        if c is None or c[0] != key:
+            c = (key, (C.c_double * len(self.tec))(*np.frombuffer(key)))
+            self.__dict__["_tec_c"] = c
+        return c[1]
+
     def beamform(self, x, stream=None):
         beamform(self.ctx, self.array, self.band, self.dirs, x, self.n_t,
                  self.dtype, self.prec, self.bufs["y"], stream)
 
     def dedisperse(self, stream=None):
         if self.plain:
-            return dedisperse_plain(self.ctx, self.band, self.tec,
+            return dedisperse_plain(self.ctx, self.band, self._tec_arg(),
                                     self.bufs["y"], self.n_beams, self.n_t,
                                     self.bufs["tail"], self.bufs["d"],
                                     self.bufs["pwork"], 0, stream)
-        dedisperse(self.ctx, self.band, self.tec, self.bufs["y"],
+        dedisperse(self.ctx, self.band, self._tec_arg(), self.bufs["y"],
                    self.n_beams, self.n_t, self.bufs["tail"], self.bufs["d"],
                    0, stream)
 
@@ -581,7 +612,7 @@ class Pipeline:
         """Both stages, one beam's group of trial_group trials at a time
         (bufs["d"] holds one group)."""
         b = self.bufs
-        dedisperse_synthesize(self.ctx, self.band, self.tec, b["y"],
+        dedisperse_synthesize(self.ctx, self.band, self._tec_arg(), b["y"],
                               self.n_beams, self.n_t, self.frame0, b["tail"],
                               b["hist"], b["cand"], self.trial_group, b["d"],
                               stream)
