@@ -171,7 +171,7 @@ def main():
     p = lp.Pipeline(ctx, lp.Array(blk.enu, 2), lp.Band(blk.k),
                     lp.Dirs(blk.az_el), blk.tec, cfg.n_t,
                     dtype=lp.LP_CI8 if cfg.dtype == "ci8" else lp.LP_CI16,
-                    prec=prec, want_series=False, device=dev)
+                    prec=prec, want_series=False, device=dev, cand_slots=2)
     stream = torch.cuda.current_stream()
     if a.calib_copy_mib:
         n = a.calib_copy_mib << 20
@@ -191,13 +191,14 @@ def main():
     print(f"[bench] first block kept for beams {sel}", file=sys.stderr,
           flush=True)
     # The trigger of block i (one workgroup per series) runs on a second
-    # stream while block i + 1 is beamformed and de-dispersed; synthesis of
-    # block i + 1 waits for it, since it overwrites the candidates.
+    # stream beside block i + 1; the candidates alternate between two
+    # buffers, so only the synthesis of block i + 2, which overwrites block
+    # i's, waits for it.
     side = torch.cuda.Stream(device=dev)      # default priority
     stages = ["beamform", "dedisperse", "synthesize", "trigger"]
 
     def run_steps(n, ev):
-        prev_trig = None
+        trig_done = []
         for i in range(n):
             e = ev[i]
             e[0].record(stream)
@@ -205,14 +206,14 @@ def main():
             e[1].record(stream)
             p.dedisperse()
             e[2].record(stream)
-            if prev_trig is not None:
-                stream.wait_event(prev_trig)
+            if len(trig_done) >= p.cand_slots:
+                stream.wait_event(trig_done[-p.cand_slots])
             p.synthesize()
             e[3].record(stream)
             side.wait_event(e[3])
             p.trigger(stream=side)
             e[4].record(side)
-            prev_trig = e[4]
+            trig_done = (trig_done + [e[4]])[-2:]
             p.frame0 += cfg.n_t
 
     def events(n):
@@ -408,8 +409,9 @@ def graph_leg(a, p, x, samples):
     graph and the trigger issued per block on the same stream (no second
     stream): the host issues two calls per block instead of four stages."""
     import torch
-    p.step_graph(x)            # capture (the stream is past its start-up)
-    torch.cuda.synchronize()
+    for _ in range(p.cand_slots):
+        p.step_graph(x)        # capture, one graph per candidate slot (the
+    torch.cuda.synchronize()   # stream is past its start-up)
     t0 = time.perf_counter()
     for _ in range(a.graph_steps):
         p.step_graph(x)
@@ -417,8 +419,9 @@ def graph_leg(a, p, x, samples):
     ms = (time.perf_counter() - t0) * 1e3 / a.graph_steps
     return {"steps": a.graph_steps, "ms_per_step": round(ms, 4),
             "value": round(samples / (ms * 1e-3) / 1e6, 1),
-            "kind": "beamform, de-dispersion and synthesis from one captured "
-                    "HIP graph; trigger per block with its frame0"}
+            "kind": "beamform, de-dispersion and synthesis from a captured "
+                    "HIP graph (one per candidate slot); trigger per block "
+                    "with its frame0 on the same stream"}
 
 
 def trial_group_leg(a, ctx, p, cfg, blk, x, ms_all):

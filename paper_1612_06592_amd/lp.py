@@ -521,6 +521,10 @@ class Pipeline:
                                  # group of this many trials at a time
     device: str = "cuda:0"
     frame0: int = 0
+    cand_slots: int = 1          # 2: the candidates of consecutive blocks
+                                 # alternate between two buffers, so block
+                                 # i's trigger can still read its own while
+                                 # block i + 1 is synthesised
     bufs: dict = field(default_factory=dict)
 
     def __post_init__(self):
@@ -533,6 +537,8 @@ class Pipeline:
             return torch.empty(n, **u8)
 
         grouped = 0 < self.trial_group and not self.plain
+        if self.cand_slots not in (1, 2):
+            raise ValueError("cand_slots must be 1 or 2")
         self.bufs = dict(
             y=buf(nbytes("lp_beam_bytes", B, S, n_t)),
             d=(buf(nbytes("lp_ddsyn_work_bytes", S, n_t,
@@ -541,6 +547,8 @@ class Pipeline:
             tail=torch.zeros(nbytes("lp_dd_state_bytes", B, S), **u8),
             hist=torch.zeros(nbytes("lp_syn_state_bytes", B * J, S), **u8),
             cand=buf(nbytes("lp_cand_bytes", B * J, n_t)),
+            **({"cand1": buf(nbytes("lp_cand_bytes", B * J, n_t))}
+               if self.cand_slots == 2 else {}),
             work=buf(nbytes("lp_trigger_work_bytes", B, J, n_t)),
             trig=torch.zeros(self.trig_cap * TRIG_DTYPE.itemsize, **u8),
             n_trig=torch.zeros(1, dtype=torch.int32, device=self.device),
@@ -564,6 +572,14 @@ class Pipeline:
     @property
     def n_tec(self):
         return len(self.tec)
+
+    def _cand(self, frame0=None):
+        """Candidate buffer of the block starting at frame0 (default: the
+        block the next stage call works on)."""
+        f = self.frame0 if frame0 is None else frame0
+        if self.cand_slots == 2 and (f // self.n_t) % 2:
+            return self.bufs["cand1"]
+        return self.bufs["cand"]
 
     def _tec_arg(self):
         """The trials as a ctypes double array, rebuilt whenever their values
@@ -594,16 +610,16 @@ class Pipeline:
             return synthesize_plain(self.ctx, self.band, self.bufs["d"],
                                     self.n_beams * self.n_tec, self.n_t,
                                     self.frame0, self.bufs["hist"],
-                                    self.bufs["cand"], self.bufs["pwork"],
+                                    self._cand(), self.bufs["pwork"],
                                     self.bufs.get("x_out"), stream)
         synthesize(self.ctx, self.band, self.bufs["d"],
                    self.n_beams * self.n_tec, self.n_t, self.frame0,
-                   self.bufs["hist"], self.bufs["cand"],
+                   self.bufs["hist"], self._cand(),
                    self.bufs.get("x_out"), stream)
 
     def trigger(self, stream=None):
         b = self.bufs
-        trigger(self.ctx, b["cand"], self.n_beams, self.n_tec, self.n_t,
+        trigger(self.ctx, self._cand(), self.n_beams, self.n_tec, self.n_t,
                 self.frame0, self.k_sigma, b["trig"], self.trig_cap,
                 b["n_trig"], b["work"], b["snr"], b["best"], b["sigma"],
                 stream)
@@ -614,7 +630,8 @@ class Pipeline:
         b = self.bufs
         dedisperse_synthesize(self.ctx, self.band, self._tec_arg(), b["y"],
                               self.n_beams, self.n_t, self.frame0, b["tail"],
-                              b["hist"], b["cand"], self.trial_group, b["d"],
+                              b["hist"], self._cand(), self.trial_group,
+                              b["d"],
                               stream)
 
     def step_graph(self, x):
@@ -631,7 +648,10 @@ class Pipeline:
         import torch
         if self.frame0 < WARM_FRAMES:
             return self.step(x)
-        g = self.bufs.get("_graph")
+        # With two candidate slots, one graph per slot (a graph holds the
+        # buffer it writes by address).
+        name = "_graph1" if self._cand() is self.bufs.get("cand1") else "_graph"
+        g = self.bufs.get(name)
         if g is None or g[1] != x.data_ptr():
             graph = torch.cuda.CUDAGraph()
             cs = torch.cuda.Stream(device=self.device)
@@ -640,7 +660,7 @@ class Pipeline:
                 self._stages(x, None)
             torch.cuda.current_stream().wait_stream(cs)
             g = (graph, x.data_ptr())
-            self.bufs["_graph"] = g
+            self.bufs[name] = g
             # (capture records the work without running it)
         g[0].replay()
         self.trigger()
@@ -683,11 +703,13 @@ class Pipeline:
         B, J, S = self.n_beams, self.n_tec, self.band.n_sb
         return self.bufs["d"].view(torch.float32).view(B, J, S, self.n_t, 2)
 
-    def cand_view(self):
-        """(emax [ns][n_t] f32, arg [ns][n_t] i32, psum [ns][n_t/16] f32)."""
+    def cand_view(self, frame0=None):
+        """(emax [ns][n_t] f32, arg [ns][n_t] i32, psum [ns][n_t/16] f32) of
+        the block starting at frame0; by default the last block step() or
+        step_graph() completed (with one candidate slot: the only buffer)."""
         import torch
         ns, n_t = self.n_beams * self.n_tec, self.n_t
-        c = self.bufs["cand"]
+        c = self._cand(self.frame0 - n_t if frame0 is None else frame0)
         head = c[: ns * n_t * 8].view(torch.int32).view(ns, n_t, 2)
         emax = head[..., 0].view(torch.float32)
         arg = head[..., 1]
