@@ -90,3 +90,44 @@ def test_dedisperse_synthesize_sizes_and_null_arguments():
                                     None)
     assert rc == lp.LP_EINVAL
     assert b"NULL" in L.lp_last_error()
+
+
+def test_binding_tec_arguments():
+    """The TEC list reaches the library as contiguous doubles whatever the
+    caller passes, a ctypes double array as it is; a pipeline's cached
+    array follows in-place edits and replacements of its trials."""
+    import numpy as np
+    arr = (C.c_double * 3)(1.0, 2.0, 3.0)
+    p, n = lp._tec(arr)
+    assert p is arr and n == 3
+    p, n = lp._tec([1.5, 2.5])
+    assert n == 2 and (p[0], p[1]) == (1.5, 2.5)
+    p, n = lp._tec(np.float32(7.0))
+    assert n == 1 and p[0] == 7.0
+    p, n = lp._tec(np.arange(8.0)[::2])        # strided: copied
+    assert n == 4 and [p[i] for i in range(4)] == [0.0, 2.0, 4.0, 6.0]
+
+    class Holder:
+        pass
+    h = Holder()
+    h.tec = np.array([0.0, 1.0, 2.0])
+    a = lp.Pipeline._tec_arg(h)
+    assert list(a) == [0.0, 1.0, 2.0]
+    assert lp.Pipeline._tec_arg(h) is a         # unchanged: cached
+    h.tec[1] = 5.0
+    b = lp.Pipeline._tec_arg(h)
+    assert list(b) == [0.0, 5.0, 2.0] and b is not a
+    h.tec = np.array([3.0])
+    assert list(lp.Pipeline._tec_arg(h)) == [3.0]
+
+
+def test_pipeline_candidate_slots_validated_before_allocation():
+    """cand_slots other than 1 or 2 is refused before any device buffer is
+    made (no GPU needed to reach the check)."""
+    import numpy as np
+    band = lp.Band(np.arange(52, 60))
+    dirs = lp.Dirs(np.array([[0.0, 1.0]]))
+    arr = lp.Array(np.zeros((2, 3)), 2)
+    for bad in (0, 3):
+        with pytest.raises(ValueError):
+            lp.Pipeline(None, arr, band, dirs, [0.0], 2048, cand_slots=bad)
