@@ -184,4 +184,45 @@ __device__ __forceinline__ int opaque(int x) {
 // LDS index with one pad slot every 16 entries (spreads banks).
 __device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
 
+// Row swaps across the wavefront (gfx950 v_permlane32/16_swap): with rows
+// of 16 lanes, swap_rows32 exchanges rows 2, 3 of a with rows 0, 1 of b;
+// swap_rows16 exchanges rows 1, 3 of a with rows 0, 2 of b.
+__device__ __forceinline__ void swap_rows32(float2 &a, float2 &b) {
+  const auto x = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.x),
+                                                  __float_as_uint(b.x), false,
+                                                  false);
+  const auto y = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.y),
+                                                  __float_as_uint(b.y), false,
+                                                  false);
+  a = make_float2(__uint_as_float(x[0]), __uint_as_float(y[0]));
+  b = make_float2(__uint_as_float(x[1]), __uint_as_float(y[1]));
+}
+__device__ __forceinline__ void swap_rows16(float2 &a, float2 &b) {
+  const auto x = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.x),
+                                                  __float_as_uint(b.x), false,
+                                                  false);
+  const auto y = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.y),
+                                                  __float_as_uint(b.y), false,
+                                                  false);
+  a = make_float2(__uint_as_float(x[0]), __uint_as_float(y[0]));
+  b = make_float2(__uint_as_float(x[1]), __uint_as_float(y[1]));
+}
+
+// After pass 1 of the 1024-point per-wave transform (radix 16, 16, 4), lane
+// j holds output (j / 16) 256 + j mod 16 + 16 r in v[r]; the radix-4
+// butterfly j + 64 q of pass 2 needs elements j + 64 q + 256 m (m < 4),
+// held in v[4 q + j / 16] of lanes j mod 16 + 16 m.  Transposing, in each
+// group of four registers, the lane's row of 16 against the register's low
+// two bits (two swap steps across rows, no LDS) leaves element
+// j + 64 q + 256 m in v[4 q + m].
+__device__ __forceinline__ void pass2_gather(float2 *v) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    swap_rows32(v[4 * q], v[4 * q + 2]);
+    swap_rows32(v[4 * q + 1], v[4 * q + 3]);
+    swap_rows16(v[4 * q], v[4 * q + 1]);
+    swap_rows16(v[4 * q + 2], v[4 * q + 3]);
+  }
+}
+
 }  // namespace lp

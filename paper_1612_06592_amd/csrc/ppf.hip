@@ -99,9 +99,9 @@ __device__ __forceinline__ void wave_lds_fence() {
 // one wave, lane j = butterfly: PASS0 also runs pass 0 on the frame in
 // natural order; otherwise pass 0's output is already in place.  No
 // workgroup barrier: the caller orders the frame's producers before and
-// its consumers after.  Slots in closed form (j < 64):
-//   pad16(j + 64 r) = j + j / 16 + 68 r,   pad16(16 j + r) = 17 j + r,
-//   pad16((j / 16) 256 + j mod 16 + 16 r) = (j / 16) 272 + j mod 16 + 17 r.
+// its consumers after.  Pass 1 hands its output to pass 2 in registers
+// (pass2_gather).  Slots in closed form (j < 64):
+//   pad16(j + 64 r) = j + j / 16 + 68 r,   pad16(16 j + r) = 17 j + r.
 template <bool INV, bool PASS0>
 __device__ __forceinline__ void fft1024_wave(float2 *fr, const float2 *tw_p1,
                                              const float2 *tw_p2, int j) {
@@ -124,15 +124,15 @@ __device__ __forceinline__ void fft1024_wave(float2 *fr, const float2 *tw_p1,
       v[r] = INV ? cmul(v[r], twr[r]) : cmulc(v[r], twr[r]);
   }
   dft16<INV>(v);
-  const int b2 = (j >> 4) * 272 + (j & 15);
-#pragma unroll
-  for (int r = 0; r < 16; ++r) fr[b2 + 17 * r] = v[r];
-  wave_lds_fence();
+  pass2_gather(v);  // v[4 q + m] = element j + 64 q + 256 m
+  // Pass 2 writes each butterfly's outputs to the slots of its inputs,
+  // pad16(j + 64 q + 256 k): the slots this lane read in pass 1.
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int jt = j + 64 * q;
     float2 *sl = fr + b1 + 68 * q;
-    float2 a0 = sl[0], a1 = sl[272], a2 = sl[544], a3 = sl[816];
+    float2 a0 = v[4 * q], a1 = v[4 * q + 1], a2 = v[4 * q + 2],
+           a3 = v[4 * q + 3];
     const float2 w1 = tw_p2[jt], w2 = tw_p2[256 + jt], w3 = tw_p2[512 + jt];
     if (INV) {
       a1 = cmul(a1, w1);

@@ -82,30 +82,6 @@ __device__ __forceinline__ unsigned wave_umax_dpp(unsigned v) {
   return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Row swaps across the wavefront (gfx950 v_permlane32/16_swap): with rows
-// of 16 lanes, swap_rows32 exchanges rows 2, 3 of a with rows 0, 1 of b;
-// swap_rows16 exchanges rows 1, 3 of a with rows 0, 2 of b.
-__device__ __forceinline__ void swap_rows32(float2 &a, float2 &b) {
-  const auto x = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.x),
-                                                  __float_as_uint(b.x), false,
-                                                  false);
-  const auto y = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.y),
-                                                  __float_as_uint(b.y), false,
-                                                  false);
-  a = make_float2(__uint_as_float(x[0]), __uint_as_float(y[0]));
-  b = make_float2(__uint_as_float(x[1]), __uint_as_float(y[1]));
-}
-__device__ __forceinline__ void swap_rows16(float2 &a, float2 &b) {
-  const auto x = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.x),
-                                                  __float_as_uint(b.x), false,
-                                                  false);
-  const auto y = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.y),
-                                                  __float_as_uint(b.y), false,
-                                                  false);
-  a = make_float2(__uint_as_float(x[0]), __uint_as_float(y[0]));
-  b = make_float2(__uint_as_float(x[1]), __uint_as_float(y[1]));
-}
-
 // MASKED: some chunk straddles the end of the warm-up (`warm` - frame0 not
 // a multiple of 16), so the statistics mask frame by frame; otherwise a
 // chunk is either all warm-up or all valid.  NR: bins j + 64 r with r >= NR
@@ -241,20 +217,7 @@ __global__ __launch_bounds__(kSynThreads) void syn_kernel(
           v[15] = cmul(v[15], cmul(w8, w7));
         }
         dft16<true>(v);
-        // Lane j now holds pass-1 output (j / 16) 256 + j mod 16 + 16 r in
-        // v[r].  The radix-4 butterfly jt = j + 64 q of pass 2 reads
-        // elements jt + 256 m (m < 4), held in v[4 q + j / 16] of lanes
-        // j mod 16 + 16 m: transposing, in each group of four registers,
-        // the lane's row of 16 (j / 16) against the register's low two bits
-        // (two swap steps across rows, no LDS) leaves element
-        // j + 64 q + 256 m in v[4 q + m].
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          swap_rows32(v[4 * q], v[4 * q + 2]);
-          swap_rows32(v[4 * q + 1], v[4 * q + 3]);
-          swap_rows16(v[4 * q], v[4 * q + 1]);
-          swap_rows16(v[4 * q + 2], v[4 * q + 3]);
-        }
+        pass2_gather(v);  // v[4 q + m] = element j + 64 q + 256 m
         // ---- pass 2 (radix 4, Ns = 256): butterflies j + 64 q, q < 4,
         // written to their output slots
         // pad16(j + 64 q + 256 k) = j + j / 16 + 68 q + 272 k (j < 64).
